@@ -1,0 +1,333 @@
+#!/usr/bin/env python3
+"""Benchmark of the resident 19-point Jacobi sweep on one MI355X.
+
+A step is one full solve of the workload on resident arrays: n_iter Jacobi
+iterations with the fused FP64 gosa of every iteration brought back to the
+host (hj_sweep). Inputs are uploaded before the timed region. The printed
+JSON line reports GLUPS (interior lattice updates per second) over the
+timed steps, the dominant kernel's algorithmic HBM bandwidth against the
+8 TB/s peak, the field and gosa error against the FP64 CPU oracle, and the
+oracle itself timed on the host cores as a reported baseline.
+
+  python bench.py [--steps K] [--warmup W] [--workload medium_f64] [--tune]
+                  [--no-cpu-baseline] [--no-extra] [--profile]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GLUPS + HBM GB/s (% of peak), FP32-batched vs FP64 plain at 1e-5 rel error"
+PEAK_HBM_GBPS = 8000.0          # MI355X HBM3E, vendor figure
+KERNEL_SOURCES = ["paper_2002_12115_amd/csrc/sweep_kernels.hpp", "paper_2002_12115_amd/csrc/sweep_types.hpp",
+                  "paper_2002_12115_amd/csrc/hj_kernels.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def interior(shape):
+    nx, ny, nz = shape
+    return (nx - 2) * (ny - 2) * (nz - 2)
+
+
+def esize(dtype: str) -> int:
+    return 8 if dtype == "f64" else 4
+
+
+def load_traffic(workload: str, cfg: dict):
+    """HBM bytes per launch measured by rocprofv3 counters, if they were taken
+    on the current kernel sources and the same launch configuration."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload)
+    if not e or e.get("kernel_hash") != kernel_hash() or e.get("config") != cfg:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(w, arrays, budget_s: float):
+    """Oracle on the host cores: whole grid, as many iterations as fit the budget."""
+    import oracle
+    nthreads = oracle.max_threads()      # OpenMP's default: OMP_NUM_THREADS or all cores
+    t0 = time.perf_counter()
+    oracle.sweep(arrays, 1, w.omega, nthreads=nthreads)
+    t1 = time.perf_counter() - t0
+    iters = max(1, min(w.iters, int(budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.sweep(arrays, iters, w.omega, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return {"value": interior(w.shape) * iters / dt / 1e9, "unit": "GLUPS", "cores": nthreads,
+            "kind": "oracle",
+            "sample": "%s grid %s, %d of %d iterations, FP64, %d OpenMP threads, %.1f s"
+                      % (w.name, "x".join(map(str, w.shape)), iters, w.iters, nthreads, dt)}
+
+
+def accuracy(w, arrays, p_gpu, hist_gpu, iters: int):
+    import oracle
+    pref, _, href = oracle.sweep(arrays, iters, w.omega, nthreads=oracle.max_threads())
+    ferr = float(np.abs(p_gpu.astype(np.float64) - pref).max() / np.abs(pref).max())
+    gerr = float(np.max(np.abs(hist_gpu - href) / href))
+    return {"field_rel_err": ferr, "gosa_rel_err": gerr, "iters_checked": iters,
+            "field_bitwise": bool(np.array_equal(p_gpu.astype(np.float64), pref))}
+
+
+def run_single(w, args, hj, inputs):
+    """Time `steps` full solves of workload w; return (result dict, solver config)."""
+    dt = np.float64 if w.dtype == "f64" else np.float32
+    log("workload", w.name, w.shape, w.dtype, "iters", w.iters)
+    t0 = time.perf_counter()
+    arrays = inputs.fields(w.seed, w.shape)      # FP64 master copies (the oracle's inputs)
+    log("inputs generated in %.1f s" % (time.perf_counter() - t0))
+    s = hj.Solver(w.dtype, w.shape)
+    t0 = time.perf_counter()
+    s.upload_all(arrays)
+    upload_s = time.perf_counter() - t0
+    log("uploaded in %.2f s" % upload_s)
+    tuned_ms = None
+    if args.tune:
+        c, tuned_ms = s.autotune(n_sweeps=args.tune_sweeps, repeats=3)
+        log("autotuned:", c, "%.3f ms per %d sweeps" % (tuned_ms, args.tune_sweeps))
+    cfg = s.config.as_dict()
+
+    # accuracy check on the first solve from the initial field
+    acc = None
+    if args.check_iters:
+        n_chk = min(args.check_iters, w.iters)
+        s.sweep(n_chk, w.omega)
+        acc = accuracy(w, arrays, s.download("p"), s.gosa_history.copy(), n_chk)
+        log("accuracy", acc)
+        s.upload("p", arrays["p"])
+
+    import torch
+    for _ in range(args.warmup):
+        s.sweep(w.iters, w.omega)
+    torch.cuda.synchronize()
+    kernel_ms = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.sweep(w.iters, w.omega)
+        kernel_ms += s.last_ms          # HIP events on the solver's stream around each solve
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    n_int = interior(w.shape)
+    updates = n_int * w.iters * args.steps
+    glups = updates / wall / 1e9
+    launches = w.iters * args.steps
+    bytes_per_launch = 14 * esize(w.dtype) * n_int
+    avg_launch_ms = kernel_ms / launches
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    traffic = load_traffic(w.name, cfg)
+    res = {
+        "glups": glups, "ms_per_step": wall * 1e3 / args.steps, "wall_s": wall,
+        "hbm_gbps_alg": achieved, "frac_peak": achieved / PEAK_HBM_GBPS,
+        "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_launch, "launches": launches,
+        "upload_s": upload_s, "pcie_inclusive_glups": updates / (wall + upload_s) / 1e9,
+        "traffic": traffic, "config": cfg, "tuned_ms": tuned_ms, "accuracy": acc,
+        "last_gosa": float(s.gosa_history[-1]),
+    }
+    s.close()
+    return res, arrays
+
+
+def run_transfer_contrast(w, args, hj, inputs, arrays, n_iter: int):
+    """The same solve with a host round trip of p every iteration."""
+    s = hj.Solver(w.dtype, w.shape)
+    s.upload_all(arrays)
+    host = np.empty(w.shape, dtype=np.float64 if w.dtype == "f64" else np.float32)
+    s.sweep(1, w.omega)
+    t0 = time.perf_counter()
+    for _ in range(n_iter):
+        s.sweep(1, w.omega)
+        host[...] = s.download("p")
+        s.upload("p", host)
+    dt = time.perf_counter() - t0
+    s.close()
+    return {"glups": interior(w.shape) * n_iter / dt / 1e9, "iters": n_iter,
+            "ms_per_iter": dt * 1e3 / n_iter}
+
+
+def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune: bool):
+    w = inputs.WORKLOADS["batch64"]
+    shapes, seeds = inputs.batch_shapes(w.seed, w.batch)
+    n_int = sum(interior(sh) for sh in shapes)
+    import torch
+    if per_instance:
+        # one launch per instance per iteration, instance after instance, FP64
+        solvers = []
+        stream = None
+        for sh, sd in zip(shapes, seeds):
+            s = hj.Solver(dtype, sh, stream=stream)   # all instances on one stream
+            stream = stream or s.stream
+            s.set(use_graph=0)
+            s.upload_all(inputs.fields(sd, sh))
+            solvers.append(s)
+        for s in solvers:
+            s.sweep_async(2, w.omega)
+        for s in solvers:
+            s.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            for s in solvers:
+                s.sweep_async(iters, w.omega)
+            for s in solvers:
+                s.sync()
+        wall = time.perf_counter() - t0
+        for s in reversed(solvers):          # the first one owns the shared stream
+            s.close()
+        cfg = None
+    else:
+        b = hj.Batch(dtype, shapes)
+        for t, (sh, sd) in enumerate(zip(shapes, seeds)):
+            b.upload_all(t, inputs.fields(sd, sh))
+        if tune:
+            c, ms = b.autotune(n_sweeps=5, repeats=3)
+            log("batch autotuned", dtype, c, ms)
+        b.sweep(2, w.omega)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            b.sweep(iters, w.omega)
+        wall = time.perf_counter() - t0
+        cfg = b.config.as_dict()
+        b.close()
+    return {"glups": n_int * iters * args.batch_steps / wall / 1e9, "dtype": dtype, "iters": iters,
+            "instances": len(shapes), "interior_cells": n_int,
+            "launches_per_iter": len(shapes) if per_instance else 1, "config": cfg,
+            "hbm_gbps_alg": 14 * esize(dtype) * n_int * iters * args.batch_steps / wall / 1e9}
+
+
+def batch_accuracy(hj, inputs, n_iter: int):
+    """FP32 batched field error against the FP64 oracle, per instance (max)."""
+    import oracle
+    w = inputs.WORKLOADS["batch64"]
+    shapes, seeds = inputs.batch_shapes(w.seed, w.batch)
+    b = hj.Batch("f32", shapes)
+    arrs = []
+    for t, (sh, sd) in enumerate(zip(shapes, seeds)):
+        a = inputs.fields(sd, sh)
+        arrs.append(a)
+        b.upload_all(t, a)
+    b.sweep(n_iter, w.omega)
+    worst = 0.0
+    for t, a in enumerate(arrs):
+        pref, _, _ = oracle.sweep(a, n_iter, w.omega, nthreads=oracle.max_threads())
+        p = b.download(t).astype(np.float64)
+        worst = max(worst, float(np.abs(p - pref).max() / np.abs(pref).max()))
+    b.close()
+    return {"field_rel_err_max": worst, "iters_checked": n_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="medium_f64")
+    ap.add_argument("--tune", action="store_true", help="autotune the kernel before timing")
+    ap.add_argument("--tune-sweeps", type=int, default=5)
+    ap.add_argument("--check-iters", type=int, default=-1,
+                    help="iterations compared with the oracle (default: all for small grids)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: no oracle, no extras")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sweep would shard as i-slabs with one halo plane exchanged per iteration)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2002_12115_amd import hj, inputs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    hj.load()
+    w = inputs.WORKLOADS[args.workload]
+    if w.batch:
+        raise SystemExit("use a single-solve workload for the main line; batch64 is reported under extra")
+    if args.profile:
+        args.no_cpu_baseline = True
+        args.no_extra = True
+        args.check_iters = 0
+    if args.check_iters < 0:
+        args.check_iters = w.iters if interior(w.shape) * w.iters <= 2e9 else 20
+
+    res, arrays = run_single(w, args, hj, inputs)
+    out = {
+        "metric": METRIC,
+        "value": res["glups"],
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w.dtype,
+        "data": "synthetic: seeded SplitMix64 fields (p~U[0,1), a,c~U[0.9,1.1), b~U[-0.05,0.05), "
+                "wrk1~N(0,0.01), derived a3 and bnd) standing in for the Himeno benchmark",
+        "config": {"workload": w.name, "grid": list(w.shape), "iters_per_step": w.iters,
+                   "omega": w.omega, "seed": w.seed, "kernel_config": res["config"]},
+        "roofline": {"bound": "hbm", "achieved": res["hbm_gbps_alg"], "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": res["frac_peak"], "traffic": res["traffic"],
+                     "kernel": "march_kernel" if res["config"]["kernel"] == 1 else "direct_kernel",
+                     "bytes_per_launch": res["bytes_per_launch"],
+                     "avg_launch_ms": res["avg_launch_ms"]},
+        "hbm_gbps_alg": res["hbm_gbps_alg"],
+        "accuracy": res["accuracy"],
+        "upload_s": res["upload_s"],
+        "pcie_inclusive_glups": res["pcie_inclusive_glups"],
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)...")
+        out["cpu_baseline"] = cpu_baseline(w, arrays, args.cpu_budget)
+    if not args.no_extra:
+        extra = {}
+        log("transfer contrast...")
+        extra["roundtrip_p_every_iteration"] = run_transfer_contrast(w, args, hj, inputs, arrays, 20)
+        log("batch64 FP32 batched...")
+        extra["batch64_f32_batched"] = run_batch(args, hj, inputs, "f32", 100, False, args.tune)
+        log("batch64 FP64 batched...")
+        extra["batch64_f64_batched"] = run_batch(args, hj, inputs, "f64", 100, False, args.tune)
+        log("batch64 FP64 one launch per instance...")
+        extra["batch64_f64_per_instance"] = run_batch(args, hj, inputs, "f64", 100, True, False)
+        extra["batch64_f32_vs_f64_per_instance"] = (extra["batch64_f32_batched"]["glups"]
+                                                    / extra["batch64_f64_per_instance"]["glups"])
+        log("batch64 FP32 accuracy...")
+        extra["batch64_f32_accuracy"] = batch_accuracy(hj, inputs, 10)
+        out["extra"] = extra
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * hj.h -- C ABI of libhj, the MI355X (gfx950) Jacobi pressure sweep.
+ *
+ * What is computed (the Himeno workload's Poisson solve by Jacobi iteration,
+ * paper section 5.1.1). The paper prints no stencil; this library fixes it as
+ * a 19-point variable-coefficient operator on an nx*ny*nz grid (k contiguous)
+ * whose one-cell shell is a Dirichlet boundary that is never written. One
+ * iteration, on every interior cell and from the field before the iteration:
+ *   s0 = a0 p(i+1,j,k) + a1 p(i,j+1,k) + a2 p(i,j,k+1)
+ *      + b0 [p(i+1,j+1,k) - p(i+1,j-1,k) - p(i-1,j+1,k) + p(i-1,j-1,k)]
+ *      + b1 [p(i,j+1,k+1) - p(i,j-1,k+1) - p(i,j+1,k-1) + p(i,j-1,k-1)]
+ *      + b2 [p(i+1,j,k+1) - p(i-1,j,k+1) - p(i+1,j,k-1) + p(i-1,j,k-1)]
+ *      + c0 p(i-1,j,k) + c1 p(i,j-1,k) + c2 p(i,j,k-1) + wrk1
+ *   ss   = (s0 a3 - p) bnd          wrk2 = p + omega ss
+ *   gosa = sum over the interior of ss^2, accumulated in FP64
+ * after which wrk2 becomes the field. Sums are evaluated left to right as
+ * written, without fused multiply-add, in FP64 (HJ_F64) or FP32 (HJ_F32;
+ * ss is widened to FP64 before it is squared).
+ *
+ * Data stays on the device. Following the paper's transfer rule (sections 3.2
+ * and 3.3: transfer once at the outermost level, mark resident data present,
+ * block implicit transfers), inputs are uploaded once, any number of sweeps
+ * run with no host transfer except the FP64 gosa values, and the field is
+ * downloaded once.
+ *
+ * Conventions for every function:
+ *  - Return 0 (HJ_OK) or a negative HJ_ERR_* code. Nothing aborts or throws.
+ *    hj_last_error() gives a thread-local message for the last failure.
+ *  - Shapes include the shell and must be >= 3 on every axis; nx*ny*nz must
+ *    fit the device. Host arrays are dense C order [nx][ny][nz], k fastest.
+ *  - Host pointers are borrowed for the duration of the call only.
+ *  - Work is ordered on the handle's HIP stream (the caller's, or one the
+ *    library creates). Calls that return host results synchronize with it.
+ *  - Different handles may be used from different threads; one handle must
+ *    not be used by two threads at once.
+ */
+#ifndef HJ_H
+#define HJ_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum hj_status {
+    HJ_OK = 0,
+    HJ_ERR_ARG = -1,     /* bad argument (null pointer, field, count, config) */
+    HJ_ERR_SHAPE = -2,   /* a dimension below 3, or sizes that overflow */
+    HJ_ERR_DTYPE = -3,   /* dtype other than HJ_F64 / HJ_F32 */
+    HJ_ERR_OOM = -4,     /* device or host allocation failed */
+    HJ_ERR_HIP = -5,     /* a HIP runtime call failed (see hj_last_error) */
+    HJ_ERR_STATE = -6,   /* e.g. sweep before every input field is uploaded */
+    HJ_ERR_HANDLE = -7,  /* null, destroyed or unknown handle */
+    HJ_ERR_TUNE = -8     /* autotuning found no candidate that passed */
+};
+
+enum hj_dtype { HJ_F64 = 0, HJ_F32 = 1 };
+
+/* Field ids: 13 inputs, then the ping-pong partner of p. */
+enum hj_field {
+    HJ_P = 0, HJ_A0, HJ_A1, HJ_A2, HJ_A3, HJ_B0, HJ_B1, HJ_B2,
+    HJ_C0, HJ_C1, HJ_C2, HJ_BND, HJ_WRK1, HJ_WRK2, HJ_NFIELDS
+};
+
+/* Kernel choice. kernel: HJ_KERNEL_DIRECT (one thread per cell, neighbours
+ * read through the caches) or HJ_KERNEL_MARCH (a (j,k) tile per workgroup
+ * marching along i, p planes staged in an LDS ring). bj: rows of 64*vec
+ * cells per workgroup (1, 2, 4, 8). vec: consecutive k cells per lane (1, 2,
+ * or 4 for HJ_F32; 1 or 2 for HJ_F64). ichunk: i planes per workgroup for the
+ * march kernel (>= 1; splits the march so the grid fills the chip).
+ * nontemporal: stream the 12 single-use arrays with non-temporal loads and
+ * stores. use_graph: replay the sweep loop as a captured HIP graph.
+ * xcd_remap: renumber workgroups so neighbouring tiles share an XCD's L2.
+ * persistent (batches only): launch as many workgroups as stay resident and
+ * let each loop over tiles, instead of one workgroup per tile. */
+typedef struct hj_config {
+    int kernel;
+    int bj;
+    int vec;
+    int ichunk;
+    int nontemporal;
+    int use_graph;
+    int xcd_remap;
+    int persistent;
+} hj_config;
+
+enum { HJ_KERNEL_DIRECT = 0, HJ_KERNEL_MARCH = 1 };
+
+typedef struct hj_solver_s* hj_solver;
+typedef struct hj_batch_s* hj_batch;
+
+/* ---- single solve ------------------------------------------------------ */
+
+/* Bytes of device memory a solve of this shape needs (for hj_attach). */
+int hj_slab_bytes(int dtype, int nx, int ny, int nz, unsigned long long* bytes);
+
+/* Create a solve that owns its device memory. stream: a hipStream_t, or
+ * NULL for a library-created non-blocking stream. */
+int hj_create(hj_solver* out, int dtype, int nx, int ny, int nz, void* stream);
+
+/* Create a solve on caller-owned device memory of at least hj_slab_bytes
+ * bytes, 256-byte aligned (e.g. a torch uint8 tensor). The caller keeps it
+ * alive and unused until hj_destroy. */
+int hj_attach(hj_solver* out, int dtype, int nx, int ny, int nz, void* device_slab,
+              unsigned long long slab_bytes, void* stream);
+
+/* Upload one input field from a dense host array in the handle's dtype
+ * (hj_upload) or in FP64 (hj_upload_f64, rounded to nearest even for HJ_F32
+ * handles). Uploading HJ_P also resets the ping-pong partner to p and makes
+ * p current. HJ_WRK2 cannot be uploaded (HJ_ERR_ARG). Synchronous. */
+int hj_upload(hj_solver h, int field, const void* host_src);
+int hj_upload_f64(hj_solver h, int field, const double* host_src);
+
+/* Download a field into a dense host array of the handle's dtype. HJ_P and
+ * HJ_WRK2 both return the current field (the last sweep's wrk2 once any
+ * sweep has run). Synchronous. */
+int hj_download(hj_solver h, int field, void* host_dst);
+
+/* Run n_iter Jacobi iterations with relaxation omega on the resident arrays.
+ * gosa_last (nullable) receives the last iteration's gosa, gosa_hist
+ * (nullable, n_iter doubles) every iteration's, each computed from the field
+ * before that iteration's update. Synchronous. n_iter == 0 is a no-op. */
+int hj_sweep(hj_solver h, int n_iter, double omega, double* gosa_last, double* gosa_hist);
+
+/* As hj_sweep, but only enqueued on the handle's stream: the per-iteration
+ * gosa goes to dev_gosa_hist (nullable device pointer, n_iter doubles). */
+int hj_sweep_async(hj_solver h, int n_iter, double omega, double* dev_gosa_hist);
+
+/* gosa of the current field, without updating it. Synchronous. */
+int hj_residual(hj_solver h, double* gosa);
+
+int hj_get_config(hj_solver h, hj_config* out);
+int hj_set_config(hj_solver h, const hj_config* cfg);
+
+/* Measure the candidate configurations on this handle's arrays and keep the
+ * fastest one whose field is bitwise equal to the reference configuration's
+ * after the same sweeps. The solve's state (p) is restored afterwards.
+ * n_sweeps per timing (>= 1), repeats (>= 1): median of repeats is scored.
+ * best (nullable) receives the chosen configuration, best_ms its time. */
+int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double* best_ms);
+
+/* Wait for all work queued on the handle's stream. */
+int hj_sync(hj_solver h);
+
+/* The HIP stream used by the handle (a hipStream_t). */
+int hj_get_stream(hj_solver h, void** stream);
+
+int hj_destroy(hj_solver h);
+
+/* ---- batch of independent solves ---------------------------------------- */
+
+/* n solves of individual shapes, all in one device slab, advanced together:
+ * each iteration is one launch over a flattened list of every instance's
+ * tiles, and the loop is replayed as a captured HIP graph. */
+int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* ny,
+                    const int* nz, void* stream);
+int hj_batch_upload(hj_batch b, int inst, int field, const void* host_src);
+int hj_batch_upload_f64(hj_batch b, int inst, int field, const double* host_src);
+int hj_batch_download(hj_batch b, int inst, int field, void* host_dst);
+
+/* gosa_last (nullable, n doubles), gosa_hist (nullable, n_iter*n doubles,
+ * [iteration][instance]). */
+int hj_batch_sweep(hj_batch b, int n_iter, double omega, double* gosa_last, double* gosa_hist);
+int hj_batch_residual(hj_batch b, double* gosa);
+int hj_batch_get_config(hj_batch b, hj_config* out);
+int hj_batch_set_config(hj_batch b, const hj_config* cfg);
+int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, double* best_ms);
+int hj_batch_destroy(hj_batch b);
+
+/* ---- diagnostics ---------------------------------------------------------- */
+
+const char* hj_status_string(int status);
+const char* hj_last_error(void);
+
+/* Device time, in milliseconds, of the last hj_sweep / hj_batch_sweep on this
+ * thread, measured with HIP events around the launched work. */
+double hj_last_sweep_ms(void);
+
+/* Stream a plain device-to-device copy of `bytes` bytes between two device
+ * buffers with the library's copy kernel (the bandwidth ceiling probe). */
+int hj_copy_probe(void* dst, const void* src, unsigned long long bytes, void* stream, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HJ_H */

@@ -1,0 +1,1320 @@
+// hj_api.hip -- libhj runtime: device layout, resident solve loop, HIP graphs,
+// batch descriptors, autotuner, and the C ABI declared in include/hj.h.
+//
+// Transfer policy (paper sections 3.2 and 3.3): every array is uploaded once
+// and stays resident; a call to hj_sweep runs all its iterations on the
+// device (as one HIP graph launch when use_graph is set) and brings back
+// only the FP64 gosa values, 8 bytes per iteration. p and wrk2 are a
+// ping-pong pair swapped by pointer, so there is no copy-back kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <exception>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "hj_launch.hpp"
+
+using namespace hj;
+
+namespace {
+
+constexpr uint64_t kSolverMagic = 0x686a736f6c766572ULL;  // "hjsolver"
+constexpr uint64_t kBatchMagic = 0x686a626174636821ULL;   // "hjbatch!"
+constexpr int kInputMask = (1 << 13) - 1;
+
+thread_local std::string g_err;
+thread_local double g_last_ms = 0.0;
+
+int set_err(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+struct HipFail {
+    hipError_t e;
+    const char* expr;
+    int line;
+};
+
+#define HIPCHK(x)                                              \
+    do {                                                       \
+        hipError_t e_ = (x);                                   \
+        if (e_ != hipSuccess) throw HipFail{e_, #x, __LINE__}; \
+    } while (0)
+
+// Run an ABI body, mapping C++ failures to status codes.
+template <typename F>
+int guarded(F&& f)
+{
+    try {
+        return f();
+    } catch (const HipFail& h) {
+        const int code = (h.e == hipErrorOutOfMemory || h.e == hipErrorMemoryAllocation) ? HJ_ERR_OOM : HJ_ERR_HIP;
+        return set_err(code, "%s failed at hj_api.hip:%d: %s (%s)", h.expr, h.line,
+                       hipGetErrorName(h.e), hipGetErrorString(h.e));
+    } catch (const std::bad_alloc&) {
+        return set_err(HJ_ERR_OOM, "host allocation failed");
+    } catch (const std::exception& e) {
+        return set_err(HJ_ERR_ARG, "exception: %s", e.what());
+    } catch (...) {
+        return set_err(HJ_ERR_ARG, "unknown exception");
+    }
+}
+
+// ---- layout -----------------------------------------------------------------
+
+// Field q of a solve lives at slab + q*field_stride. Inside it, element
+// (i,j,k) is at element offset (A-1) + i*S + j*P + k, where A = 128 bytes /
+// element size: every row's k = 1 starts on a 128-byte line, P is a multiple
+// of A and leaves room after k = nz-1 for the widest vector over-read. The
+// field stride carries a 2304-byte stagger (9 * 256 B) so the 14 streams of a
+// sweep start at different offsets modulo the DRAM interleave.
+struct Layout {
+    int nx = 0, ny = 0, nz = 0, esz = 0, A = 0;
+    long long P = 0, S = 0;
+    size_t field_bytes = 0, field_stride = 0, slab_bytes = 0;
+};
+
+size_t stagger_bytes()
+{
+    static size_t s = [] {
+        const char* e = getenv("HJ_STAGGER");
+        long v = e ? atol(e) : 2304;
+        if (v < 0) v = 0;
+        return (size_t)((v + 255) / 256 * 256);
+    }();
+    return s;
+}
+
+bool make_layout(int dtype, int nx, int ny, int nz, Layout& L)
+{
+    if (nx < 3 || ny < 3 || nz < 3) return false;
+    if (nx > (1 << 20) || ny > (1 << 20) || nz > (1 << 24)) return false;
+    L.nx = nx; L.ny = ny; L.nz = nz;
+    L.esz = dtype == HJ_F64 ? 8 : 4;
+    L.A = 128 / L.esz;
+    L.P = ((long long)L.A + nz + 4 + L.A - 1) / L.A * L.A;
+    L.S = (long long)ny * L.P;
+    const long double bytes = (long double)nx * L.S * L.esz;
+    if (bytes > (long double)(1ULL << 46)) return false;
+    L.field_bytes = (size_t)nx * (size_t)L.S * (size_t)L.esz;
+    L.field_stride = (L.field_bytes + 65535) / 65536 * 65536 + stagger_bytes();
+    L.slab_bytes = (size_t)HJ_NFIELDS * L.field_stride;
+    return true;
+}
+
+int check_dtype(int dtype)
+{
+    if (dtype != HJ_F64 && dtype != HJ_F32) return set_err(HJ_ERR_DTYPE, "dtype %d is not HJ_F64 or HJ_F32", dtype);
+    return HJ_OK;
+}
+
+hj_config default_config(int dtype)
+{
+    hj_config c;
+    c.kernel = HJ_KERNEL_MARCH;
+    c.bj = 4;
+    c.vec = dtype == HJ_F64 ? 1 : 2;
+    c.ichunk = 16;
+    c.nontemporal = 1;
+    c.use_graph = 1;
+    c.xcd_remap = 1;
+    c.persistent = 0;
+    return c;
+}
+
+bool same_config(const hj_config& a, const hj_config& b) { return memcmp(&a, &b, sizeof a) == 0; }
+
+// Reference configuration of the autotuner's parity gate: the plainest kernel.
+hj_config reference_config(int dtype)
+{
+    hj_config c = default_config(dtype);
+    c.kernel = HJ_KERNEL_DIRECT;
+    c.bj = 4;
+    c.vec = 1;
+    c.nontemporal = 0;
+    c.xcd_remap = 0;
+    return c;
+}
+
+// ---- device buffers -----------------------------------------------------------
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t need)
+    {
+        if (need <= bytes) return;
+        release();
+        HIPCHK(hipMalloc(&p, need));
+        bytes = need;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+struct PinBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t need)
+    {
+        if (need <= bytes) return;
+        release();
+        HIPCHK(hipHostMalloc(&p, need, hipHostMallocDefault));
+        bytes = need;
+    }
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+struct GraphEntry {
+    int n_iter;
+    uint64_t omega_bits;
+    int parity;
+    hj_config cfg;
+    double* out;
+    hipGraphExec_t exec;
+};
+
+uint64_t bits_of(double x)
+{
+    uint64_t u;
+    memcpy(&u, &x, 8);
+    return u;
+}
+
+// Iterations whose per-tile gosa partials are kept before a finalize.
+int chunk_iters(int n_iter, long long tiles)
+{
+    long long ch = std::min<long long>(256, n_iter);
+    const long long cap = (32LL << 20) / std::max<long long>(1, tiles);  // <= 256 MiB of partials
+    ch = std::max<long long>(1, std::min(ch, cap));
+    return (int)ch;
+}
+
+struct GraphCache {
+    std::vector<GraphEntry> v;
+    hipGraphExec_t find(int n, double omega, int parity, const hj_config& c, double* out)
+    {
+        for (auto& e : v)
+            if (e.n_iter == n && e.omega_bits == bits_of(omega) && e.parity == parity &&
+                same_config(e.cfg, c) && e.out == out)
+                return e.exec;
+        return nullptr;
+    }
+    void add(const GraphEntry& e)
+    {
+        if (v.size() >= 8) {
+            (void)hipGraphExecDestroy(v.front().exec);
+            v.erase(v.begin());
+        }
+        v.push_back(e);
+    }
+    void clear()
+    {
+        for (auto& e : v) (void)hipGraphExecDestroy(e.exec);
+        v.clear();
+    }
+};
+
+template <typename Enq>
+hipGraphExec_t capture(hipStream_t cap, Enq&& enqueue)
+{
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue(cap);
+    } catch (...) {
+        hipGraph_t g2 = nullptr;
+        (void)hipStreamEndCapture(cap, &g2);
+        if (g2) (void)hipGraphDestroy(g2);
+        throw;
+    }
+    HIPCHK(hipStreamEndCapture(cap, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHK(e);
+    return exec;
+}
+
+std::mutex g_reg_mu;
+std::set<void*> g_registry;
+
+void reg_add(void* h)
+{
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_registry.insert(h);
+}
+bool reg_has(void* h)
+{
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    return g_registry.count(h) != 0;
+}
+void reg_del(void* h)
+{
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_registry.erase(h);
+}
+
+int median_index_sort(std::vector<float>& t)
+{
+    std::sort(t.begin(), t.end());
+    return (int)(t.size() / 2);
+}
+
+}  // namespace
+
+// ============================================================================
+// single solve
+// ============================================================================
+
+struct hj_solver_s {
+    uint64_t magic = kSolverMagic;
+    int dtype = HJ_F64;
+    Layout L;
+    char* slab = nullptr;
+    bool owns_slab = false;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    hipStream_t cap = nullptr;
+    int parity = 0;           // 0: field HJ_P holds the current p, 1: field HJ_WRK2 does
+    unsigned uploaded = 0;
+    hj_config cfg;
+    DevBuf part, gosa;
+    PinBuf host_gosa;
+    GraphCache graphs;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    char* field(int q) const { return slab + (size_t)q * L.field_stride; }
+    // element (0,0,0) of field q
+    char* origin(int q) const { return field(q) + (size_t)(L.A - 1) * L.esz; }
+
+    template <typename T>
+    Grid<T> grid(int par) const
+    {
+        Grid<T> g;
+        for (int q = 0; q < NCOEF; ++q) g.coef[q] = reinterpret_cast<const T*>(origin(HJ_A0 + q));
+        g.src = reinterpret_cast<const T*>(origin(par ? HJ_WRK2 : HJ_P));
+        g.dst = reinterpret_cast<T*>(origin(par ? HJ_P : HJ_WRK2));
+        g.nx = L.nx; g.ny = L.ny; g.nz = L.nz; g.P = L.P; g.S = L.S;
+        return g;
+    }
+
+    long long tiles() const { return tile_counts(cfg, L.nx, L.ny, L.nz).tiles(); }
+
+    hipError_t launch_one(int par, double omega, bool write, double* part_out, hipStream_t st) const
+    {
+        if (dtype == HJ_F64) return launch_sweep<double>(cfg, grid<double>(par), omega, write, part_out, st);
+        return launch_sweep<float>(cfg, grid<float>(par), (float)omega, write, part_out, st);
+    }
+
+    // Enqueue n_iter sweeps starting from parity `par`, gosa history to out.
+    void enqueue(int n_iter, double omega, int par, double* out, hipStream_t st) const
+    {
+        const long long nt = tiles();
+        const int ch = chunk_iters(n_iter, nt);
+        double* pt = static_cast<double*>(part.p);
+        int it0 = 0;
+        for (int it = 0; it < n_iter; ++it) {
+            const int slot = it - it0;
+            HIPCHK(launch_one(par, omega, true, pt + (long long)slot * nt, st));
+            par ^= 1;
+            if (slot + 1 == ch || it == n_iter - 1) {
+                HIPCHK(launch_finalize(pt, nt, (int)nt, nullptr, 1, slot + 1, out + it0, st));
+                it0 = it + 1;
+            }
+        }
+    }
+
+    void reserve(int n_iter)
+    {
+        const long long nt = tiles();
+        const size_t need_part = (size_t)chunk_iters(std::max(n_iter, 1), nt) * (size_t)nt * 8;
+        const size_t need_gosa = (size_t)std::max(n_iter, 1) * 8;
+        if (need_part > part.bytes || need_gosa > gosa.bytes) {
+            graphs.clear();  // graphs hold the old addresses
+            part.ensure(need_part);
+            gosa.ensure(need_gosa);
+        }
+    }
+
+    // Enqueue the whole loop on `stream`, as a graph replay when configured.
+    void run(int n_iter, double omega, double* out)
+    {
+        if (cfg.use_graph) {
+            hipGraphExec_t ex = graphs.find(n_iter, omega, parity, cfg, out);
+            if (!ex) {
+                const int par = parity;
+                ex = capture(cap, [&](hipStream_t s) { enqueue(n_iter, omega, par, out, s); });
+                graphs.add(GraphEntry{n_iter, bits_of(omega), parity, cfg, out, ex});
+            }
+            HIPCHK(hipGraphLaunch(ex, stream));
+        } else {
+            enqueue(n_iter, omega, parity, out, stream);
+        }
+        parity ^= (n_iter & 1);
+    }
+};
+
+namespace {
+
+int check_solver(hj_solver h)
+{
+    if (!h || !reg_has(h) || h->magic != kSolverMagic)
+        return set_err(HJ_ERR_HANDLE, "invalid or destroyed hj_solver handle");
+    return HJ_OK;
+}
+
+int solver_init(hj_solver* out, int dtype, int nx, int ny, int nz, void* dev_slab,
+                unsigned long long slab_bytes, void* stream)
+{
+    if (!out) return set_err(HJ_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (int rc = check_dtype(dtype)) return rc;
+    Layout L;
+    if (!make_layout(dtype, nx, ny, nz, L))
+        return set_err(HJ_ERR_SHAPE, "shape %dx%dx%d is invalid (each >= 3, within limits)", nx, ny, nz);
+    if (dev_slab) {
+        if (slab_bytes < L.slab_bytes)
+            return set_err(HJ_ERR_ARG, "slab of %llu bytes is smaller than the %zu needed", slab_bytes, L.slab_bytes);
+        if (reinterpret_cast<uintptr_t>(dev_slab) % 256)
+            return set_err(HJ_ERR_ARG, "device slab must be 256-byte aligned");
+    }
+    hj_solver h = new hj_solver_s();
+    h->dtype = dtype;
+    h->L = L;
+    h->cfg = default_config(dtype);
+    try {
+        if (dev_slab) {
+            h->slab = static_cast<char*>(dev_slab);
+        } else {
+            HIPCHK(hipMalloc(reinterpret_cast<void**>(&h->slab), L.slab_bytes));
+            h->owns_slab = true;
+        }
+        if (stream) {
+            h->stream = static_cast<hipStream_t>(stream);
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+            h->owns_stream = true;
+        }
+        HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        HIPCHK(hipEventCreate(&h->ev0));
+        HIPCHK(hipEventCreate(&h->ev1));
+    } catch (...) {
+        if (h->owns_slab && h->slab) (void)hipFree(h->slab);
+        if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
+        if (h->cap) (void)hipStreamDestroy(h->cap);
+        if (h->ev0) (void)hipEventDestroy(h->ev0);
+        if (h->ev1) (void)hipEventDestroy(h->ev1);
+        delete h;
+        throw;
+    }
+    reg_add(h);
+    *out = h;
+    return HJ_OK;
+}
+
+// Host <-> device copies of one dense field.
+void copy_in(const Layout& L, char* field, const void* src, hipStream_t st)
+{
+    char* dst = field + (size_t)(L.A - 1) * L.esz;
+    HIPCHK(hipMemcpy2DAsync(dst, (size_t)L.P * L.esz, src, (size_t)L.nz * L.esz, (size_t)L.nz * L.esz,
+                            (size_t)L.nx * L.ny, hipMemcpyHostToDevice, st));
+}
+
+void copy_out(const Layout& L, const char* field, void* dst, hipStream_t st)
+{
+    const char* src = field + (size_t)(L.A - 1) * L.esz;
+    HIPCHK(hipMemcpy2DAsync(dst, (size_t)L.nz * L.esz, src, (size_t)L.P * L.esz, (size_t)L.nz * L.esz,
+                            (size_t)L.nx * L.ny, hipMemcpyDeviceToHost, st));
+}
+
+std::vector<float> to_f32(const double* src, size_t n)
+{
+    std::vector<float> v(n);
+    for (size_t q = 0; q < n; ++q) v[q] = (float)src[q];  // round to nearest even
+    return v;
+}
+
+int validate_config(int dtype, const hj_config* c)
+{
+    if (!c) return set_err(HJ_ERR_ARG, "config is NULL");
+    if (!config_supported(dtype, *c))
+        return set_err(HJ_ERR_ARG, "unsupported config kernel=%d bj=%d vec=%d ichunk=%d for dtype %d",
+                       c->kernel, c->bj, c->vec, c->ichunk, dtype);
+    return HJ_OK;
+}
+
+// Candidate configurations of the autotuner for one grid.
+std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch)
+{
+    std::vector<hj_config> out;
+    const hj_config base = default_config(dtype);
+    if (!batch) {
+        for (int bj : {2, 4, 8})
+            for (int nt : {0, 1}) {
+                hj_config c = base;
+                c.kernel = HJ_KERNEL_DIRECT;
+                c.bj = bj;
+                c.vec = 1;
+                c.nontemporal = nt;
+                c.xcd_remap = 0;
+                out.push_back(c);
+            }
+    }
+    const int ni = nx - 2;
+    std::vector<int> vecs = dtype == HJ_F64 ? std::vector<int>{1, 2} : std::vector<int>{1, 2, 4};
+    for (int bj : {1, 2, 4, 8})
+        for (int v : vecs) {
+            const long long kt = (nz - 2 + 64 * v - 1) / (64 * v);
+            const long long jt = (ny - 2 + bj - 1) / bj;
+            const long long base_tiles = kt * jt;
+            std::vector<int> ich;
+            for (long long target : {512LL, 1024LL, 2048LL, 4096LL}) {
+                long long nchunks = (target + base_tiles - 1) / base_tiles;
+                int c = (int)std::max<long long>(2, (ni + nchunks - 1) / nchunks);
+                c = std::min(c, std::max(ni, 1));
+                if (std::find(ich.begin(), ich.end(), c) == ich.end()) ich.push_back(c);
+            }
+            for (int c : ich)
+                for (int nt : {0, 1})
+                    for (int rm : {0, 1}) {
+                        hj_config x = base;
+                        x.kernel = HJ_KERNEL_MARCH;
+                        x.bj = bj;
+                        x.vec = v;
+                        x.ichunk = c;
+                        x.nontemporal = nt;
+                        x.xcd_remap = batch ? 0 : rm;
+                        x.persistent = batch ? rm : 0;
+                        if (config_supported(dtype, x)) out.push_back(x);
+                    }
+        }
+    return out;
+}
+
+// A default i-chunk that gives the grid a few thousand workgroups.
+int default_ichunk(int dtype, const hj_config& c, int nx, int ny, int nz)
+{
+    const long long kt = (nz - 2 + 64 * c.vec - 1) / (64 * c.vec);
+    const long long jt = (ny - 2 + c.bj - 1) / c.bj;
+    const long long target = 2048;
+    const long long nchunks = std::max<long long>(1, (target + kt * jt - 1) / (kt * jt));
+    (void)dtype;
+    return (int)std::max<long long>(4, (nx - 2 + nchunks - 1) / nchunks);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hj_status_string(int s)
+{
+    switch (s) {
+    case HJ_OK: return "HJ_OK";
+    case HJ_ERR_ARG: return "HJ_ERR_ARG";
+    case HJ_ERR_SHAPE: return "HJ_ERR_SHAPE";
+    case HJ_ERR_DTYPE: return "HJ_ERR_DTYPE";
+    case HJ_ERR_OOM: return "HJ_ERR_OOM";
+    case HJ_ERR_HIP: return "HJ_ERR_HIP";
+    case HJ_ERR_STATE: return "HJ_ERR_STATE";
+    case HJ_ERR_HANDLE: return "HJ_ERR_HANDLE";
+    case HJ_ERR_TUNE: return "HJ_ERR_TUNE";
+    default: return "HJ_ERR_UNKNOWN";
+    }
+}
+
+const char* hj_last_error(void) { return g_err.c_str(); }
+
+double hj_last_sweep_ms(void) { return g_last_ms; }
+
+int hj_slab_bytes(int dtype, int nx, int ny, int nz, unsigned long long* bytes)
+{
+    if (!bytes) return set_err(HJ_ERR_ARG, "bytes is NULL");
+    if (int rc = check_dtype(dtype)) return rc;
+    Layout L;
+    if (!make_layout(dtype, nx, ny, nz, L)) return set_err(HJ_ERR_SHAPE, "invalid shape %dx%dx%d", nx, ny, nz);
+    *bytes = L.slab_bytes;
+    return HJ_OK;
+}
+
+int hj_create(hj_solver* out, int dtype, int nx, int ny, int nz, void* stream)
+{
+    return guarded([&]() -> int {
+        const int rc = solver_init(out, dtype, nx, ny, nz, nullptr, 0, stream);
+        if (rc == HJ_OK) (*out)->cfg.ichunk = default_ichunk(dtype, (*out)->cfg, nx, ny, nz);
+        return rc;
+    });
+}
+
+int hj_attach(hj_solver* out, int dtype, int nx, int ny, int nz, void* device_slab,
+              unsigned long long slab_bytes, void* stream)
+{
+    if (!device_slab) return set_err(HJ_ERR_ARG, "device_slab is NULL");
+    return guarded([&]() -> int {
+        const int rc = solver_init(out, dtype, nx, ny, nz, device_slab, slab_bytes, stream);
+        if (rc == HJ_OK) (*out)->cfg.ichunk = default_ichunk(dtype, (*out)->cfg, nx, ny, nz);
+        return rc;
+    });
+}
+
+int hj_upload(hj_solver h, int field, const void* src)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (!src) return set_err(HJ_ERR_ARG, "host_src is NULL");
+    if (field == HJ_WRK2) return set_err(HJ_ERR_ARG, "HJ_WRK2 is derived from HJ_P and cannot be uploaded");
+    if (field < 0 || field >= HJ_WRK2) return set_err(HJ_ERR_ARG, "field %d out of range", field);
+    return guarded([&]() -> int {
+        if (field == HJ_P) {
+            copy_in(h->L, h->field(HJ_P), src, h->stream);
+            copy_in(h->L, h->field(HJ_WRK2), src, h->stream);
+            h->parity = 0;
+        } else {
+            copy_in(h->L, h->field(field), src, h->stream);
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->uploaded |= 1u << field;
+        return HJ_OK;
+    });
+}
+
+int hj_upload_f64(hj_solver h, int field, const double* src)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (!src) return set_err(HJ_ERR_ARG, "host_src is NULL");
+    if (h->dtype == HJ_F64) return hj_upload(h, field, src);
+    return guarded([&]() -> int {
+        std::vector<float> v = to_f32(src, (size_t)h->L.nx * h->L.ny * h->L.nz);
+        return hj_upload(h, field, v.data());
+    });
+}
+
+int hj_download(hj_solver h, int field, void* dst)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (!dst) return set_err(HJ_ERR_ARG, "host_dst is NULL");
+    if (field < 0 || field >= HJ_NFIELDS) return set_err(HJ_ERR_ARG, "field %d out of range", field);
+    return guarded([&]() -> int {
+        int q = field;
+        if (field == HJ_P || field == HJ_WRK2) q = h->parity ? HJ_WRK2 : HJ_P;
+        copy_out(h->L, h->field(q), dst, h->stream);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return HJ_OK;
+    });
+}
+
+int hj_sweep(hj_solver h, int n_iter, double omega, double* gosa_last, double* gosa_hist)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (n_iter < 0) return set_err(HJ_ERR_ARG, "n_iter %d < 0", n_iter);
+    if ((h->uploaded & kInputMask) != (unsigned)kInputMask)
+        return set_err(HJ_ERR_STATE, "not every input field is uploaded (mask 0x%x)", h->uploaded);
+    if (n_iter == 0) return HJ_OK;
+    return guarded([&]() -> int {
+        h->reserve(n_iter);
+        double* out = static_cast<double*>(h->gosa.p);
+        HIPCHK(hipEventRecord(h->ev0, h->stream));
+        h->run(n_iter, omega, out);
+        HIPCHK(hipEventRecord(h->ev1, h->stream));
+        h->host_gosa.ensure((size_t)n_iter * 8);
+        HIPCHK(hipMemcpyAsync(h->host_gosa.p, out, (size_t)n_iter * 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        g_last_ms = ms;
+        const double* hg = static_cast<const double*>(h->host_gosa.p);
+        if (gosa_hist) memcpy(gosa_hist, hg, (size_t)n_iter * 8);
+        if (gosa_last) *gosa_last = hg[n_iter - 1];
+        return HJ_OK;
+    });
+}
+
+int hj_sweep_async(hj_solver h, int n_iter, double omega, double* dev_gosa_hist)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (n_iter < 0) return set_err(HJ_ERR_ARG, "n_iter %d < 0", n_iter);
+    if ((h->uploaded & kInputMask) != (unsigned)kInputMask)
+        return set_err(HJ_ERR_STATE, "not every input field is uploaded (mask 0x%x)", h->uploaded);
+    if (n_iter == 0) return HJ_OK;
+    return guarded([&]() -> int {
+        h->reserve(n_iter);
+        double* out = dev_gosa_hist ? dev_gosa_hist : static_cast<double*>(h->gosa.p);
+        h->run(n_iter, omega, out);
+        return HJ_OK;
+    });
+}
+
+int hj_residual(hj_solver h, double* gosa)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (!gosa) return set_err(HJ_ERR_ARG, "gosa is NULL");
+    if ((h->uploaded & kInputMask) != (unsigned)kInputMask)
+        return set_err(HJ_ERR_STATE, "not every input field is uploaded (mask 0x%x)", h->uploaded);
+    return guarded([&]() -> int {
+        h->reserve(1);
+        double* pt = static_cast<double*>(h->part.p);
+        double* out = static_cast<double*>(h->gosa.p);
+        const long long nt = h->tiles();
+        HIPCHK(h->launch_one(h->parity, 0.0, false, pt, h->stream));
+        HIPCHK(launch_finalize(pt, nt, (int)nt, nullptr, 1, 1, out, h->stream));
+        h->host_gosa.ensure(8);
+        HIPCHK(hipMemcpyAsync(h->host_gosa.p, out, 8, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        *gosa = *static_cast<const double*>(h->host_gosa.p);
+        return HJ_OK;
+    });
+}
+
+int hj_get_config(hj_solver h, hj_config* out)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (!out) return set_err(HJ_ERR_ARG, "out is NULL");
+    *out = h->cfg;
+    return HJ_OK;
+}
+
+int hj_set_config(hj_solver h, const hj_config* cfg)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (int rc = validate_config(h->dtype, cfg)) return rc;
+    return guarded([&]() -> int {
+        h->graphs.clear();
+        h->cfg = *cfg;
+        h->cfg.persistent = 0;
+        return HJ_OK;
+    });
+}
+
+int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double* best_ms)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (n_sweeps < 1 || repeats < 1) return set_err(HJ_ERR_ARG, "n_sweeps and repeats must be >= 1");
+    if ((h->uploaded & kInputMask) != (unsigned)kInputMask)
+        return set_err(HJ_ERR_STATE, "not every input field is uploaded");
+    return guarded([&]() -> int {
+        const Layout& L = h->L;
+        const hj_config keep = h->cfg;
+        DevBuf save, ref, cnt;
+        save.ensure(L.field_bytes);
+        ref.ensure(L.field_bytes);
+        cnt.ensure(8);
+        const int par0 = h->parity;
+        HIPCHK(hipMemcpyAsync(save.p, h->field(par0 ? HJ_WRK2 : HJ_P), L.field_bytes, hipMemcpyDeviceToDevice, h->stream));
+        auto restore = [&] {
+            HIPCHK(hipMemcpyAsync(h->field(HJ_P), save.p, L.field_bytes, hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(hipMemcpyAsync(h->field(HJ_WRK2), save.p, L.field_bytes, hipMemcpyDeviceToDevice, h->stream));
+            h->parity = 0;
+        };
+        std::vector<hj_config> cands = candidates(h->dtype, L.nx, L.ny, L.nz, false);
+        cands.insert(cands.begin(), reference_config(h->dtype));
+        hj_config win = keep;
+        double win_ms = INFINITY;
+        bool have_ref = false;
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            hj_config c = cands[ci];
+            c.use_graph = 0;
+            h->graphs.clear();
+            h->cfg = c;
+            restore();
+            h->reserve(n_sweeps);
+            double* out = static_cast<double*>(h->gosa.p);
+            // one run for the parity gate (and warm-up)
+            try {
+                h->run(n_sweeps, 0.8, out);
+            } catch (const HipFail&) {
+                (void)hipGetLastError();
+                continue;  // a candidate that does not launch scores as infinitely slow
+            }
+            const char* cur = h->field(h->parity ? HJ_WRK2 : HJ_P);
+            if (!have_ref) {
+                HIPCHK(hipMemcpyAsync(ref.p, cur, L.field_bytes, hipMemcpyDeviceToDevice, h->stream));
+                have_ref = true;
+            } else {
+                unsigned long long bad = 0;
+                HIPCHK(hipMemcpyAsync(cnt.p, &bad, 8, hipMemcpyHostToDevice, h->stream));
+                HIPCHK(launch_diff(cur, ref.p, L.field_bytes, static_cast<unsigned long long*>(cnt.p), h->stream));
+                HIPCHK(hipMemcpyAsync(&bad, cnt.p, 8, hipMemcpyDeviceToHost, h->stream));
+                HIPCHK(hipStreamSynchronize(h->stream));
+                if (bad) continue;  // not bitwise equal to the reference: rejected
+            }
+            if (ci == 0 && cands.size() > 1) continue;  // reference itself is not a contender
+            std::vector<float> t;
+            for (int r = 0; r < repeats; ++r) {
+                HIPCHK(hipEventRecord(h->ev0, h->stream));
+                h->run(n_sweeps, 0.8, out);
+                HIPCHK(hipEventRecord(h->ev1, h->stream));
+                HIPCHK(hipEventSynchronize(h->ev1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+                t.push_back(ms);
+            }
+            const double med = t[median_index_sort(t)];
+            if (med < win_ms) {
+                win_ms = med;
+                win = c;
+            }
+        }
+        restore();
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->graphs.clear();
+        if (!std::isfinite(win_ms)) {
+            h->cfg = keep;
+            return set_err(HJ_ERR_TUNE, "no candidate configuration passed");
+        }
+        win.use_graph = keep.use_graph;
+        h->cfg = win;
+        if (best) *best = win;
+        if (best_ms) *best_ms = win_ms;
+        return HJ_OK;
+    });
+}
+
+int hj_sync(hj_solver h)
+{
+    if (int rc = check_solver(h)) return rc;
+    return guarded([&]() -> int {
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return HJ_OK;
+    });
+}
+
+int hj_get_stream(hj_solver h, void** stream)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (!stream) return set_err(HJ_ERR_ARG, "stream is NULL");
+    *stream = h->stream;
+    return HJ_OK;
+}
+
+int hj_destroy(hj_solver h)
+{
+    if (int rc = check_solver(h)) return rc;
+    reg_del(h);
+    (void)hipStreamSynchronize(h->stream);
+    h->graphs.clear();
+    h->part.release();
+    h->gosa.release();
+    h->host_gosa.release();
+    if (h->owns_slab) (void)hipFree(h->slab);
+    if (h->owns_stream) (void)hipStreamDestroy(h->stream);
+    (void)hipStreamDestroy(h->cap);
+    (void)hipEventDestroy(h->ev0);
+    (void)hipEventDestroy(h->ev1);
+    h->magic = 0;
+    delete h;
+    return HJ_OK;
+}
+
+int hj_copy_probe(void* dst, const void* src, unsigned long long bytes, void* stream, double* ms)
+{
+    if (!dst || !src) return set_err(HJ_ERR_ARG, "null buffer");
+    if (bytes % 16) return set_err(HJ_ERR_ARG, "bytes must be a multiple of 16");
+    return guarded([&]() -> int {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        HIPCHK(hipEventRecord(a, st));
+        hipError_t e = launch_copy(dst, src, bytes, st);
+        HIPCHK(hipEventRecord(b, st));
+        HIPCHK(hipEventSynchronize(b));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        HIPCHK(e);
+        if (ms) *ms = t;
+        return HJ_OK;
+    });
+}
+
+}  // extern "C"
+
+// ============================================================================
+// batch of independent solves
+// ============================================================================
+
+struct hj_batch_s {
+    uint64_t magic = kBatchMagic;
+    int dtype = HJ_F32;
+    int n = 0;
+    std::vector<Layout> L;
+    std::vector<size_t> off;       // byte offset of each instance in the slab
+    char* slab = nullptr;
+    size_t slab_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    hipStream_t cap = nullptr;
+    int parity = 0;
+    std::vector<unsigned> uploaded;
+    hj_config cfg;
+    int cus = 256;
+    // tile list of the current configuration
+    DevBuf d_inst, d_tile_inst, d_seg;
+    int ntiles = 0, grid = 0;
+    hj_config tiled_for;
+    bool tiled = false;
+    DevBuf part, gosa;
+    PinBuf host_gosa;
+    GraphCache graphs;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    char* field(int inst, int q) const { return slab + off[inst] + (size_t)q * L[inst].field_stride; }
+    char* origin(int inst, int q) const { return field(inst, q) + (size_t)(L[inst].A - 1) * L[inst].esz; }
+
+    template <typename T>
+    void build_tiles_t()
+    {
+        std::vector<Instance<T>> inst(n);
+        std::vector<int> tile_inst;
+        std::vector<int> seg(n + 1, 0);
+        for (int t = 0; t < n; ++t) {
+            const Layout& l = L[t];
+            Instance<T>& d = inst[t];
+            d.f[0] = reinterpret_cast<T*>(origin(t, HJ_P));
+            d.f[1] = reinterpret_cast<T*>(origin(t, HJ_WRK2));
+            for (int q = 0; q < NCOEF; ++q) d.coef[q] = reinterpret_cast<const T*>(origin(t, HJ_A0 + q));
+            d.nx = l.nx; d.ny = l.ny; d.nz = l.nz; d.P = l.P; d.S = l.S;
+            const TileCounts tc = tile_counts(cfg, l.nx, l.ny, l.nz);
+            d.kt_n = tc.kt_n;
+            d.jt_n = tc.jt_n;
+            d.ichunk = cfg.ichunk;
+            d.tile0 = (int)tile_inst.size();
+            seg[t] = d.tile0;
+            const long long nt = tc.tiles();
+            if (tile_inst.size() + nt > 0x7fffffffLL) throw std::bad_alloc();
+            tile_inst.insert(tile_inst.end(), (size_t)nt, t);
+        }
+        seg[n] = (int)tile_inst.size();
+        ntiles = (int)tile_inst.size();
+        d_inst.ensure(sizeof(Instance<T>) * std::max(n, 1));
+        d_tile_inst.ensure(sizeof(int) * std::max(ntiles, 1));
+        d_seg.ensure(sizeof(int) * (n + 1));
+        HIPCHK(hipMemcpy(d_inst.p, inst.data(), sizeof(Instance<T>) * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_tile_inst.p, tile_inst.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_seg.p, seg.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+        if (cfg.persistent) {
+            const int occ = batch_occupancy<T>(cfg);
+            grid = std::max(1, std::min(ntiles, std::max(occ, 1) * cus));
+        } else {
+            grid = ntiles;
+        }
+    }
+
+    void build_tiles()
+    {
+        if (tiled && same_config(tiled_for, cfg)) return;
+        graphs.clear();
+        if (dtype == HJ_F64) build_tiles_t<double>();
+        else build_tiles_t<float>();
+        tiled_for = cfg;
+        tiled = true;
+    }
+
+    hipError_t launch_one(int par, double omega, bool write, double* part_out, hipStream_t st) const
+    {
+        if (dtype == HJ_F64)
+            return launch_batch<double>(cfg, static_cast<const Instance<double>*>(d_inst.p),
+                                        static_cast<const int*>(d_tile_inst.p), ntiles, grid, par, omega,
+                                        write, part_out, st);
+        return launch_batch<float>(cfg, static_cast<const Instance<float>*>(d_inst.p),
+                                   static_cast<const int*>(d_tile_inst.p), ntiles, grid, par, (float)omega,
+                                   write, part_out, st);
+    }
+
+    void enqueue(int n_iter, double omega, int par, double* out, hipStream_t st) const
+    {
+        const int ch = chunk_iters(n_iter, ntiles);
+        double* pt = static_cast<double*>(part.p);
+        int it0 = 0;
+        for (int it = 0; it < n_iter; ++it) {
+            const int slot = it - it0;
+            HIPCHK(launch_one(par, omega, true, pt + (long long)slot * ntiles, st));
+            par ^= 1;
+            if (slot + 1 == ch || it == n_iter - 1) {
+                HIPCHK(launch_finalize(pt, ntiles, ntiles, static_cast<const int*>(d_seg.p), n, slot + 1,
+                                       out + (long long)it0 * n, st));
+                it0 = it + 1;
+            }
+        }
+    }
+
+    void reserve(int n_iter)
+    {
+        build_tiles();
+        const size_t need_part = (size_t)chunk_iters(std::max(n_iter, 1), ntiles) * (size_t)std::max(ntiles, 1) * 8;
+        const size_t need_gosa = (size_t)std::max(n_iter, 1) * (size_t)n * 8;
+        if (need_part > part.bytes || need_gosa > gosa.bytes) {
+            graphs.clear();
+            part.ensure(need_part);
+            gosa.ensure(need_gosa);
+        }
+    }
+
+    void run(int n_iter, double omega, double* out)
+    {
+        if (cfg.use_graph) {
+            hipGraphExec_t ex = graphs.find(n_iter, omega, parity, cfg, out);
+            if (!ex) {
+                const int par = parity;
+                ex = capture(cap, [&](hipStream_t s) { enqueue(n_iter, omega, par, out, s); });
+                graphs.add(GraphEntry{n_iter, bits_of(omega), parity, cfg, out, ex});
+            }
+            HIPCHK(hipGraphLaunch(ex, stream));
+        } else {
+            enqueue(n_iter, omega, parity, out, stream);
+        }
+        parity ^= (n_iter & 1);
+    }
+
+    bool all_uploaded() const
+    {
+        for (unsigned u : uploaded)
+            if ((u & kInputMask) != (unsigned)kInputMask) return false;
+        return true;
+    }
+};
+
+namespace {
+
+int check_batch(hj_batch b)
+{
+    if (!b || !reg_has(b) || b->magic != kBatchMagic)
+        return set_err(HJ_ERR_HANDLE, "invalid or destroyed hj_batch handle");
+    return HJ_OK;
+}
+
+hj_config batch_default(int dtype)
+{
+    hj_config c = default_config(dtype);
+    c.kernel = HJ_KERNEL_MARCH;
+    c.bj = 4;
+    c.vec = 1;
+    c.ichunk = 16;
+    c.xcd_remap = 0;
+    c.persistent = 0;
+    return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* ny, const int* nz,
+                    void* stream)
+{
+    if (!out) return set_err(HJ_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (int rc = check_dtype(dtype)) return rc;
+    if (n < 1 || !nx || !ny || !nz) return set_err(HJ_ERR_ARG, "need n >= 1 and shape arrays");
+    return guarded([&]() -> int {
+        hj_batch b = new hj_batch_s();
+        b->dtype = dtype;
+        b->n = n;
+        b->L.resize(n);
+        b->off.resize(n);
+        b->uploaded.assign(n, 0u);
+        size_t total = 0;
+        for (int t = 0; t < n; ++t) {
+            if (!make_layout(dtype, nx[t], ny[t], nz[t], b->L[t])) {
+                delete b;
+                return set_err(HJ_ERR_SHAPE, "instance %d: invalid shape %dx%dx%d", t, nx[t], ny[t], nz[t]);
+            }
+            b->off[t] = total;
+            total += b->L[t].slab_bytes;
+        }
+        b->slab_bytes = total;
+        b->cfg = batch_default(dtype);
+        try {
+            HIPCHK(hipMalloc(reinterpret_cast<void**>(&b->slab), total));
+            if (stream) {
+                b->stream = static_cast<hipStream_t>(stream);
+            } else {
+                HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+                b->owns_stream = true;
+            }
+            HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+            HIPCHK(hipEventCreate(&b->ev0));
+            HIPCHK(hipEventCreate(&b->ev1));
+            int dev = 0;
+            HIPCHK(hipGetDevice(&dev));
+            HIPCHK(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev));
+        } catch (...) {
+            if (b->slab) (void)hipFree(b->slab);
+            if (b->owns_stream && b->stream) (void)hipStreamDestroy(b->stream);
+            if (b->cap) (void)hipStreamDestroy(b->cap);
+            if (b->ev0) (void)hipEventDestroy(b->ev0);
+            if (b->ev1) (void)hipEventDestroy(b->ev1);
+            delete b;
+            throw;
+        }
+        reg_add(b);
+        *out = b;
+        return HJ_OK;
+    });
+}
+
+int hj_batch_upload(hj_batch b, int inst, int field, const void* src)
+{
+    if (int rc = check_batch(b)) return rc;
+    if (inst < 0 || inst >= b->n) return set_err(HJ_ERR_ARG, "instance %d out of range", inst);
+    if (!src) return set_err(HJ_ERR_ARG, "host_src is NULL");
+    if (field == HJ_WRK2) return set_err(HJ_ERR_ARG, "HJ_WRK2 cannot be uploaded");
+    if (field < 0 || field >= HJ_WRK2) return set_err(HJ_ERR_ARG, "field %d out of range", field);
+    return guarded([&]() -> int {
+        if (field == HJ_P) {
+            // the pair shares one parity: keep the instance's current buffer
+            // and its partner identical so any parity is valid
+            copy_in(b->L[inst], b->field(inst, HJ_P), src, b->stream);
+            copy_in(b->L[inst], b->field(inst, HJ_WRK2), src, b->stream);
+        } else {
+            copy_in(b->L[inst], b->field(inst, field), src, b->stream);
+        }
+        HIPCHK(hipStreamSynchronize(b->stream));
+        b->uploaded[inst] |= 1u << field;
+        return HJ_OK;
+    });
+}
+
+int hj_batch_upload_f64(hj_batch b, int inst, int field, const double* src)
+{
+    if (int rc = check_batch(b)) return rc;
+    if (inst < 0 || inst >= b->n) return set_err(HJ_ERR_ARG, "instance %d out of range", inst);
+    if (!src) return set_err(HJ_ERR_ARG, "host_src is NULL");
+    if (b->dtype == HJ_F64) return hj_batch_upload(b, inst, field, src);
+    return guarded([&]() -> int {
+        const Layout& l = b->L[inst];
+        std::vector<float> v = to_f32(src, (size_t)l.nx * l.ny * l.nz);
+        return hj_batch_upload(b, inst, field, v.data());
+    });
+}
+
+int hj_batch_download(hj_batch b, int inst, int field, void* dst)
+{
+    if (int rc = check_batch(b)) return rc;
+    if (inst < 0 || inst >= b->n) return set_err(HJ_ERR_ARG, "instance %d out of range", inst);
+    if (!dst) return set_err(HJ_ERR_ARG, "host_dst is NULL");
+    if (field < 0 || field >= HJ_NFIELDS) return set_err(HJ_ERR_ARG, "field %d out of range", field);
+    return guarded([&]() -> int {
+        int q = field;
+        if (field == HJ_P || field == HJ_WRK2) q = b->parity ? HJ_WRK2 : HJ_P;
+        copy_out(b->L[inst], b->field(inst, q), dst, b->stream);
+        HIPCHK(hipStreamSynchronize(b->stream));
+        return HJ_OK;
+    });
+}
+
+int hj_batch_sweep(hj_batch b, int n_iter, double omega, double* gosa_last, double* gosa_hist)
+{
+    if (int rc = check_batch(b)) return rc;
+    if (n_iter < 0) return set_err(HJ_ERR_ARG, "n_iter %d < 0", n_iter);
+    if (!b->all_uploaded()) return set_err(HJ_ERR_STATE, "not every input field of every instance is uploaded");
+    if (n_iter == 0) return HJ_OK;
+    return guarded([&]() -> int {
+        b->reserve(n_iter);
+        double* out = static_cast<double*>(b->gosa.p);
+        HIPCHK(hipEventRecord(b->ev0, b->stream));
+        b->run(n_iter, omega, out);
+        HIPCHK(hipEventRecord(b->ev1, b->stream));
+        const size_t nbytes = (size_t)n_iter * b->n * 8;
+        b->host_gosa.ensure(nbytes);
+        HIPCHK(hipMemcpyAsync(b->host_gosa.p, out, nbytes, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+        g_last_ms = ms;
+        const double* hg = static_cast<const double*>(b->host_gosa.p);
+        if (gosa_hist) memcpy(gosa_hist, hg, nbytes);
+        if (gosa_last) memcpy(gosa_last, hg + (size_t)(n_iter - 1) * b->n, (size_t)b->n * 8);
+        return HJ_OK;
+    });
+}
+
+int hj_batch_residual(hj_batch b, double* gosa)
+{
+    if (int rc = check_batch(b)) return rc;
+    if (!gosa) return set_err(HJ_ERR_ARG, "gosa is NULL");
+    if (!b->all_uploaded()) return set_err(HJ_ERR_STATE, "not every input field of every instance is uploaded");
+    return guarded([&]() -> int {
+        b->reserve(1);
+        double* pt = static_cast<double*>(b->part.p);
+        double* out = static_cast<double*>(b->gosa.p);
+        HIPCHK(b->launch_one(b->parity, 0.0, false, pt, b->stream));
+        HIPCHK(launch_finalize(pt, b->ntiles, b->ntiles, static_cast<const int*>(b->d_seg.p), b->n, 1, out,
+                               b->stream));
+        b->host_gosa.ensure((size_t)b->n * 8);
+        HIPCHK(hipMemcpyAsync(b->host_gosa.p, out, (size_t)b->n * 8, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        memcpy(gosa, b->host_gosa.p, (size_t)b->n * 8);
+        return HJ_OK;
+    });
+}
+
+int hj_batch_get_config(hj_batch b, hj_config* out)
+{
+    if (int rc = check_batch(b)) return rc;
+    if (!out) return set_err(HJ_ERR_ARG, "out is NULL");
+    *out = b->cfg;
+    return HJ_OK;
+}
+
+int hj_batch_set_config(hj_batch b, const hj_config* cfg)
+{
+    if (int rc = check_batch(b)) return rc;
+    if (int rc = validate_config(b->dtype, cfg)) return rc;
+    if (cfg->kernel != HJ_KERNEL_MARCH) return set_err(HJ_ERR_ARG, "batches run the march kernel only");
+    return guarded([&]() -> int {
+        b->graphs.clear();
+        b->cfg = *cfg;
+        b->cfg.xcd_remap = 0;
+        return HJ_OK;
+    });
+}
+
+int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, double* best_ms)
+{
+    if (int rc = check_batch(b)) return rc;
+    if (n_sweeps < 1 || repeats < 1) return set_err(HJ_ERR_ARG, "n_sweeps and repeats must be >= 1");
+    if (!b->all_uploaded()) return set_err(HJ_ERR_STATE, "not every input field of every instance is uploaded");
+    return guarded([&]() -> int {
+        const hj_config keep = b->cfg;
+        DevBuf save, ref, cnt;
+        save.ensure(b->slab_bytes);
+        ref.ensure(b->slab_bytes);
+        cnt.ensure(8);
+        const int par0 = b->parity;
+        HIPCHK(hipMemcpyAsync(save.p, b->slab, b->slab_bytes, hipMemcpyDeviceToDevice, b->stream));
+        auto restore = [&] {
+            HIPCHK(hipMemcpyAsync(b->slab, save.p, b->slab_bytes, hipMemcpyDeviceToDevice, b->stream));
+            b->parity = par0;
+        };
+        // the biggest instance shapes the candidate list
+        int mx = 0;
+        for (int t = 1; t < b->n; ++t)
+            if ((long long)b->L[t].nx * b->L[t].ny * b->L[t].nz > (long long)b->L[mx].nx * b->L[mx].ny * b->L[mx].nz) mx = t;
+        long long cells = 0;
+        for (auto& l : b->L) cells += (long long)(l.nx - 2) * (l.ny - 2) * (l.nz - 2);
+        std::vector<hj_config> cands;
+        const int vmax = b->dtype == HJ_F64 ? 2 : 4;
+        for (int bj : {1, 2, 4, 8})
+            for (int v = 1; v <= vmax; v *= 2)
+                for (int ich : {4, 8, 16, 32})
+                    for (int nt : {0, 1})
+                        for (int per : {0, 1}) {
+                            hj_config c = batch_default(b->dtype);
+                            c.bj = bj; c.vec = v; c.ichunk = ich; c.nontemporal = nt; c.persistent = per;
+                            if (config_supported(b->dtype, c)) cands.push_back(c);
+                        }
+        (void)cells;
+        hj_config refc = batch_default(b->dtype);
+        refc.nontemporal = 0;
+        cands.insert(cands.begin(), refc);
+        hj_config win = keep;
+        double win_ms = INFINITY;
+        bool have_ref = false;
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            hj_config c = cands[ci];
+            c.use_graph = 1;
+            b->cfg = c;
+            restore();
+            double* out = nullptr;
+            try {
+                b->reserve(n_sweeps);
+                out = static_cast<double*>(b->gosa.p);
+                b->run(n_sweeps, 0.8, out);
+            } catch (const HipFail&) {
+                (void)hipGetLastError();
+                continue;
+            }
+            if (!have_ref) {
+                HIPCHK(hipMemcpyAsync(ref.p, b->slab, b->slab_bytes, hipMemcpyDeviceToDevice, b->stream));
+                have_ref = true;
+            } else {
+                unsigned long long bad = 0;
+                HIPCHK(hipMemcpyAsync(cnt.p, &bad, 8, hipMemcpyHostToDevice, b->stream));
+                HIPCHK(launch_diff(b->slab, ref.p, b->slab_bytes, static_cast<unsigned long long*>(cnt.p), b->stream));
+                HIPCHK(hipMemcpyAsync(&bad, cnt.p, 8, hipMemcpyDeviceToHost, b->stream));
+                HIPCHK(hipStreamSynchronize(b->stream));
+                if (bad) continue;
+            }
+            if (ci == 0 && cands.size() > 1) continue;
+            std::vector<float> t;
+            for (int r = 0; r < repeats; ++r) {
+                HIPCHK(hipEventRecord(b->ev0, b->stream));
+                b->run(n_sweeps, 0.8, out);
+                HIPCHK(hipEventRecord(b->ev1, b->stream));
+                HIPCHK(hipEventSynchronize(b->ev1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+                t.push_back(ms);
+            }
+            const double med = t[median_index_sort(t)];
+            if (med < win_ms) {
+                win_ms = med;
+                win = c;
+            }
+        }
+        restore();
+        HIPCHK(hipStreamSynchronize(b->stream));
+        b->graphs.clear();
+        if (!std::isfinite(win_ms)) {
+            b->cfg = keep;
+            b->tiled = false;
+            return set_err(HJ_ERR_TUNE, "no candidate configuration passed");
+        }
+        win.use_graph = keep.use_graph;
+        b->cfg = win;
+        if (best) *best = win;
+        if (best_ms) *best_ms = win_ms;
+        return HJ_OK;
+    });
+}
+
+int hj_batch_destroy(hj_batch b)
+{
+    if (int rc = check_batch(b)) return rc;
+    reg_del(b);
+    (void)hipStreamSynchronize(b->stream);
+    b->graphs.clear();
+    b->part.release();
+    b->gosa.release();
+    b->host_gosa.release();
+    b->d_inst.release();
+    b->d_tile_inst.release();
+    b->d_seg.release();
+    (void)hipFree(b->slab);
+    if (b->owns_stream) (void)hipStreamDestroy(b->stream);
+    (void)hipStreamDestroy(b->cap);
+    (void)hipEventDestroy(b->ev0);
+    (void)hipEventDestroy(b->ev1);
+    b->magic = 0;
+    delete b;
+    return HJ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+// hj_kernels.hip -- instantiation and dispatch of the sweep kernels.
+#include "hj_launch.hpp"
+#include "sweep_kernels.hpp"
+
+namespace hj {
+
+namespace {
+
+template <typename T> constexpr bool vec_ok(int v) { return v == 1 || v == 2 || (sizeof(T) == 4 && v == 4); }
+constexpr bool bj_ok(int b) { return b == 1 || b == 2 || b == 4 || b == 8; }
+
+template <typename T, int BJ, int V, bool NT, bool W>
+hipError_t march_go(const hj_config& c, const Grid<T>& g, T omega, double* part, hipStream_t st)
+{
+    const TileCounts t = tile_counts(c, g.nx, g.ny, g.nz);
+    const long long nb = t.tiles();
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((march_kernel<T, BJ, V, NT, W>), dim3((unsigned)nb), dim3(kWave * BJ), 0, st,
+                       g, omega, c.ichunk, t.kt_n, t.jt_n, c.xcd_remap, part);
+    return hipGetLastError();
+}
+
+template <typename T, int BJ, int V, bool NT, bool W>
+hipError_t direct_go(const hj_config& c, const Grid<T>& g, T omega, double* part, hipStream_t st)
+{
+    const TileCounts t = tile_counts(c, g.nx, g.ny, g.nz);
+    const long long nb = t.tiles();
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((direct_kernel<T, BJ, NT, W>), dim3((unsigned)nb), dim3(kWave * BJ), 0, st,
+                       g, omega, t.kt_n, t.jt_n, c.xcd_remap, part);
+    return hipGetLastError();
+}
+
+template <typename T, int BJ, int V, bool NT, bool W>
+hipError_t batch_go(const Instance<T>* inst, const int* tile_inst, int ntiles, int grid,
+                    int parity, T omega, double* part, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((batch_kernel<T, BJ, V, NT, W>), dim3(grid), dim3(kWave * BJ), 0, st,
+                       inst, tile_inst, ntiles, parity, omega, part);
+    return hipGetLastError();
+}
+
+template <typename T, int BJ, int V, bool NT>
+int batch_occ()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<T, BJ, V, NT, true>,
+                                                     kWave * BJ, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
+// Expand the run-time (bj, vec, nt, write) choice into a template instance.
+#define HJ_DISPATCH_W(FN, T, BJ, V, NT, ...)                                 \
+    (write ? FN<T, BJ, V, NT, true>(__VA_ARGS__) : FN<T, BJ, V, NT, false>(__VA_ARGS__))
+#define HJ_DISPATCH_NT(FN, T, BJ, V, ...)                                    \
+    (c.nontemporal ? HJ_DISPATCH_W(FN, T, BJ, V, true, __VA_ARGS__)          \
+                   : HJ_DISPATCH_W(FN, T, BJ, V, false, __VA_ARGS__))
+
+template <typename T, int BJ>
+hipError_t march_bj(const hj_config& c, const Grid<T>& g, T omega, bool write, double* part,
+                    hipStream_t st)
+{
+    switch (c.vec) {
+    case 1: return HJ_DISPATCH_NT(march_go, T, BJ, 1, c, g, omega, part, st);
+    case 2: return HJ_DISPATCH_NT(march_go, T, BJ, 2, c, g, omega, part, st);
+    case 4:
+        if constexpr (sizeof(T) == 4) return HJ_DISPATCH_NT(march_go, T, BJ, 4, c, g, omega, part, st);
+        else return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int BJ, int V>
+hipError_t batch_v(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
+                   int grid, int parity, T omega, bool write, double* part, hipStream_t st)
+{
+    return HJ_DISPATCH_NT(batch_go, T, BJ, V, inst, tile_inst, ntiles, grid, parity, omega, part, st);
+}
+
+template <typename T, int BJ>
+hipError_t batch_bj(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
+                    int grid, int parity, T omega, bool write, double* part, hipStream_t st)
+{
+    switch (c.vec) {
+    case 1: return batch_v<T, BJ, 1>(c, inst, tile_inst, ntiles, grid, parity, omega, write, part, st);
+    case 2: return batch_v<T, BJ, 2>(c, inst, tile_inst, ntiles, grid, parity, omega, write, part, st);
+    case 4:
+        if constexpr (sizeof(T) == 4)
+            return batch_v<T, BJ, 4>(c, inst, tile_inst, ntiles, grid, parity, omega, write, part, st);
+        else return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int BJ>
+int batch_occ_bj(const hj_config& c)
+{
+    switch (c.vec) {
+    case 1: return c.nontemporal ? batch_occ<T, BJ, 1, true>() : batch_occ<T, BJ, 1, false>();
+    case 2: return c.nontemporal ? batch_occ<T, BJ, 2, true>() : batch_occ<T, BJ, 2, false>();
+    case 4:
+        if constexpr (sizeof(T) == 4)
+            return c.nontemporal ? batch_occ<T, BJ, 4, true>() : batch_occ<T, BJ, 4, false>();
+        else return 0;
+    default: return 0;
+    }
+}
+
+}  // namespace
+
+bool config_supported(int dtype, const hj_config& c)
+{
+    if (dtype != HJ_F64 && dtype != HJ_F32) return false;
+    if (!bj_ok(c.bj)) return false;
+    if (c.kernel == HJ_KERNEL_DIRECT) return c.bj >= 2;
+    if (c.kernel != HJ_KERNEL_MARCH) return false;
+    if (c.ichunk < 1) return false;
+    return dtype == HJ_F64 ? vec_ok<double>(c.vec) : vec_ok<float>(c.vec);
+}
+
+template <typename T>
+hipError_t launch_sweep(const hj_config& c, const Grid<T>& g, T omega, bool write, double* part,
+                        hipStream_t st)
+{
+    if (c.kernel == HJ_KERNEL_DIRECT) {
+        switch (c.bj) {
+        case 2: return HJ_DISPATCH_NT(direct_go, T, 2, 1, c, g, omega, part, st);
+        case 4: return HJ_DISPATCH_NT(direct_go, T, 4, 1, c, g, omega, part, st);
+        case 8: return HJ_DISPATCH_NT(direct_go, T, 8, 1, c, g, omega, part, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (c.bj) {
+    case 1: return march_bj<T, 1>(c, g, omega, write, part, st);
+    case 2: return march_bj<T, 2>(c, g, omega, write, part, st);
+    case 4: return march_bj<T, 4>(c, g, omega, write, part, st);
+    case 8: return march_bj<T, 8>(c, g, omega, write, part, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_batch(const hj_config& c, const Instance<T>* inst, const int* tile_inst,
+                        int ntiles, int grid, int parity, T omega, bool write, double* part,
+                        hipStream_t st)
+{
+    switch (c.bj) {
+    case 1: return batch_bj<T, 1>(c, inst, tile_inst, ntiles, grid, parity, omega, write, part, st);
+    case 2: return batch_bj<T, 2>(c, inst, tile_inst, ntiles, grid, parity, omega, write, part, st);
+    case 4: return batch_bj<T, 4>(c, inst, tile_inst, ntiles, grid, parity, omega, write, part, st);
+    case 8: return batch_bj<T, 8>(c, inst, tile_inst, ntiles, grid, parity, omega, write, part, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+int batch_occupancy(const hj_config& c)
+{
+    switch (c.bj) {
+    case 1: return batch_occ_bj<T, 1>(c);
+    case 2: return batch_occ_bj<T, 2>(c);
+    case 4: return batch_occ_bj<T, 4>(c);
+    case 8: return batch_occ_bj<T, 8>(c);
+    default: return 0;
+    }
+}
+
+template hipError_t launch_sweep<double>(const hj_config&, const Grid<double>&, double, bool,
+                                         double*, hipStream_t);
+template hipError_t launch_sweep<float>(const hj_config&, const Grid<float>&, float, bool, double*,
+                                        hipStream_t);
+template hipError_t launch_batch<double>(const hj_config&, const Instance<double>*, const int*, int,
+                                         int, int, double, bool, double*, hipStream_t);
+template hipError_t launch_batch<float>(const hj_config&, const Instance<float>*, const int*, int,
+                                        int, int, float, bool, double*, hipStream_t);
+template int batch_occupancy<double>(const hj_config&);
+template int batch_occupancy<float>(const hj_config&);
+
+hipError_t launch_finalize(const double* part, long long stride, int n, const int* seg_begin,
+                           int nseg, int nslots, double* out, hipStream_t st)
+{
+    if (nslots <= 0 || nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3(nseg, nslots), dim3(256), 0, st, part, stride, n,
+                       seg_begin, nseg, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, unsigned long long bytes, hipStream_t st)
+{
+    const long long n16 = (long long)(bytes / 16);
+    if (n16 <= 0) return hipSuccess;
+    long long blocks = (n16 + 255) / 256;
+    if (blocks > 256LL * 32) blocks = 256LL * 32;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                       reinterpret_cast<const u32x4*>(src), reinterpret_cast<u32x4*>(dst), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_diff(const void* a, const void* b, unsigned long long bytes,
+                       unsigned long long* count, hipStream_t st)
+{
+    const long long n4 = (long long)(bytes / 4);
+    if (n4 <= 0) return hipSuccess;
+    long long blocks = (n4 + 255) / 256;
+    if (blocks > 256LL * 16) blocks = 256LL * 16;
+    hipLaunchKernelGGL(diff_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                       reinterpret_cast<const uint32_t*>(a), reinterpret_cast<const uint32_t*>(b),
+                       n4, count);
+    return hipGetLastError();
+}
+
+}  // namespace hj

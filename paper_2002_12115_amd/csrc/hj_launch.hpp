@@ -1,0 +1,54 @@
+// hj_launch.hpp -- host-side launchers of the sweep kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/hj.h"
+#include "sweep_types.hpp"
+
+namespace hj {
+
+struct TileCounts {
+    int kt_n, jt_n, ic_n;
+    long long tiles() const { return (long long)kt_n * jt_n * ic_n; }
+};
+
+inline int vec_of(const hj_config& c) { return c.kernel == HJ_KERNEL_DIRECT ? 1 : c.vec; }
+
+inline TileCounts tile_counts(const hj_config& c, int nx, int ny, int nz)
+{
+    TileCounts t;
+    const int tk = kWave * vec_of(c);
+    t.kt_n = (nz - 2 + tk - 1) / tk;
+    t.jt_n = (ny - 2 + c.bj - 1) / c.bj;
+    t.ic_n = c.kernel == HJ_KERNEL_DIRECT ? nx - 2 : chunks(nx, c.ichunk);
+    return t;
+}
+
+// True when (dtype, config) names an instantiated kernel.
+bool config_supported(int dtype, const hj_config& c);
+
+// One sweep (write) or residual (no write) over a single grid. part receives
+// one FP64 partial per tile (tile_counts(...).tiles() of them).
+template <typename T>
+hipError_t launch_sweep(const hj_config& c, const Grid<T>& g, T omega, bool write, double* part,
+                        hipStream_t st);
+
+// One iteration over every instance of a batch.
+template <typename T>
+hipError_t launch_batch(const hj_config& c, const Instance<T>* inst, const int* tile_inst,
+                        int ntiles, int grid, int parity, T omega, bool write, double* part,
+                        hipStream_t st);
+
+// Workgroups per CU the batch kernel of this configuration can keep resident.
+template <typename T>
+int batch_occupancy(const hj_config& c);
+
+hipError_t launch_finalize(const double* part, long long stride, int n, const int* seg_begin,
+                           int nseg, int nslots, double* out, hipStream_t st);
+
+hipError_t launch_copy(void* dst, const void* src, unsigned long long bytes, hipStream_t st);
+
+hipError_t launch_diff(const void* a, const void* b, unsigned long long bytes,
+                       unsigned long long* count, hipStream_t st);
+
+}  // namespace hj

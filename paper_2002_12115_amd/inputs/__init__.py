@@ -62,6 +62,8 @@ def _load():
         lib.hjgen_fill_f64.argtypes = [u64, i32, i32, i32, i32, dbl, i32, vp]
         lib.hjgen_fill_f32.restype = i32
         lib.hjgen_fill_f32.argtypes = [u64, i32, i32, i32, i32, dbl, i32, vp]
+        lib.hjgen_values_f64.restype = i32
+        lib.hjgen_values_f64.argtypes = [u64, i32, i32, i32, i32, dbl, i32, ctypes.c_longlong, vp, vp]
         lib.hjgen_batch.restype = i32
         lib.hjgen_batch.argtypes = [u64, i32, i32, i32, i32, i32, vp, vp, vp, vp]
         _lib = lib
@@ -107,6 +109,42 @@ def field(seed: int, name, shape: Sequence[int], dtype=np.float64,
         raise ValueError("dtype must be float64 or float32")
     if rc != 0:
         raise ValueError("hjgen rejected field=%d shape=%s" % (fid, (nx, ny, nz)))
+    return out
+
+
+def values(seed: int, name, shape: Sequence[int], idx, sigma: float = DEFAULT_SIGMA,
+           bnd_mode: int = 0) -> np.ndarray:
+    """FP64 values of one field at the given dense linear indices of a grid."""
+    fid = FIELD_ID[name] if isinstance(name, str) else int(name)
+    nx, ny, nz = (int(s) for s in shape)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty(idx.shape, dtype=np.float64)
+    rc = _load().hjgen_values_f64(seed & 0xFFFFFFFFFFFFFFFF, fid, nx, ny, nz, sigma, bnd_mode,
+                                  int(idx.size), idx.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("hjgen_values rejected field=%r or an index" % (name,))
+    return out
+
+
+def neighbourhood(seed: int, shape: Sequence[int], centres, sigma: float = DEFAULT_SIGMA,
+                  bnd_mode: int = 0, dtype=np.float64) -> Dict[str, np.ndarray]:
+    """The 13 inputs on the 3x3x3 block around each interior centre (i,j,k).
+
+    Returns arrays of shape [m, 3, 3, 3]; block q holds cells (i-1..i+1,
+    j-1..j+1, k-1..k+1) of centre q, with the values the full grid has there
+    (rounded to `dtype`, then widened back to FP64).
+    """
+    nx, ny, nz = (int(s) for s in shape)
+    c = np.asarray(centres, dtype=np.int64).reshape(-1, 3)
+    d = np.arange(-1, 2)
+    ii = c[:, 0, None, None, None] + d[None, :, None, None]
+    jj = c[:, 1, None, None, None] + d[None, None, :, None]
+    kk = c[:, 2, None, None, None] + d[None, None, None, :]
+    lin = (ii * ny + jj) * nz + kk
+    out = {}
+    for n in INPUTS:
+        v = values(seed, n, shape, lin.ravel(), sigma, bnd_mode).reshape(lin.shape)
+        out[n] = v.astype(dtype).astype(np.float64)
     return out
 
 

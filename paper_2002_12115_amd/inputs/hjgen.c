@@ -166,3 +166,19 @@ int hjgen_batch(uint64_t seed, int n_inst, int lo_xy, int hi_xy, int lo_z, int h
     }
     return 0;
 }
+
+/* Values of field `field` at selected dense linear indices of an
+ * [nx][ny][nz] grid (any order, any count): the same numbers hjgen_fill_f64
+ * puts at those positions. */
+int hjgen_values_f64(uint64_t seed, int field, int nx, int ny, int nz, double sigma,
+                     int bnd_mode, long long count, const long long* idx, double* out)
+{
+    if (field < 0 || field > 12 || nx < 1 || ny < 1 || nz < 1 || !idx || !out) return -1;
+    const long long total = (long long)nx * ny * nz;
+    for (long long q = 0; q < count; ++q)
+        if (idx[q] < 0 || idx[q] >= total) return -1;
+#pragma omp parallel for schedule(static)
+    for (long long q = 0; q < count; ++q)
+        out[q] = field_value(seed, field, nx, ny, nz, (uint64_t)idx[q], sigma, bnd_mode);
+    return 0;
+}

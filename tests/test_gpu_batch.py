@@ -1,0 +1,103 @@
+"""GPU parity of the batched path: every instance of one launch-per-iteration
+batch equals its own single solve and the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2002_12115_amd import hj, inputs
+from _hjtest import F32_FIELD_RTOL, F64_GOSA_RTOL, field_err, gosa_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch(seed=2002, n=7):
+    shapes, seeds = inputs.batch_shapes(seed, n, lo_xy=3, hi_xy=21, lo_z=3, hi_z=80)
+    shapes[0] = (3, 3, 3)          # a single-cell interior among the others
+    return shapes, seeds
+
+
+def batch_configs(dtype):
+    out = []
+    vmax = 2 if dtype == "f64" else 4
+    for bj in (1, 2, 4, 8):
+        v = 1
+        while v <= vmax:
+            for ich, nt, per in ((1, 1, 0), (5, 0, 1), (64, 1, 1)):
+                out.append(hj.Config.make(kernel=1, bj=bj, vec=v, ichunk=ich, nontemporal=nt,
+                                          use_graph=1, xcd_remap=0, persistent=per))
+            v *= 2
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_matches_oracle_every_config(dtype):
+    shapes, seeds = small_batch()
+    arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
+    refs = [oracle.sweep(a, 6, 0.8, nthreads=4) for a in arrays]
+    for c in batch_configs(dtype):
+        say("batch", dtype, c)
+        with hj.Batch(dtype, shapes) as b:
+            b.config = c
+            for t, a in enumerate(arrays):
+                b.upload_all(t, a)
+            b.sweep(6, 0.8)
+            hist = b.gosa_history
+            for t in range(len(shapes)):
+                p = b.download(t, "p")
+                pref, _, href = refs[t]
+                if dtype == "f64":
+                    assert np.array_equal(p, pref), (t, shapes[t])
+                    assert gosa_err(hist[:, t], href) <= F64_GOSA_RTOL
+                else:
+                    assert field_err(p, pref) <= F32_FIELD_RTOL, (t, shapes[t])
+
+
+def test_batch_equals_single_solves_bitwise():
+    shapes, seeds = inputs.batch_shapes(7, 5, lo_xy=10, hi_xy=40, lo_z=20, hi_z=150)
+    arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
+    for dtype in ("f64", "f32"):
+        say("batch vs single", dtype)
+        with hj.Batch(dtype, shapes) as b:
+            for t, a in enumerate(arrays):
+                b.upload_all(t, a)
+            b.sweep(9, 0.8)
+            hist = b.gosa_history.copy()
+            res = b.residual()
+            outs = [b.download(t) for t in range(len(shapes))]
+        for t, a in enumerate(arrays):
+            with hj.Solver(dtype, shapes[t]) as s:
+                s.upload_all(a)
+                s.sweep(9, 0.8)
+                assert np.array_equal(s.download(), outs[t])
+                assert gosa_err(hist[:, t], s.gosa_history) < 1e-12
+                assert res[t] == pytest.approx(s.residual(), rel=1e-12)
+
+
+def test_batch_autotune_keeps_parity():
+    shapes, seeds = small_batch(1, 5)
+    arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
+    with hj.Batch("f64", shapes) as b:
+        for t, a in enumerate(arrays):
+            b.upload_all(t, a)
+        say("batch autotune")
+        best, ms = b.autotune(n_sweeps=2, repeats=1)
+        assert ms > 0 and best.kernel == 1
+        b.sweep(4, 0.8)
+        for t, a in enumerate(arrays):
+            pref, _, _ = oracle.sweep(a, 4, 0.8)
+            assert np.array_equal(b.download(t), pref)
+
+
+def test_batch_errors():
+    with pytest.raises(hj.HJError) as e:
+        hj.Batch("f64", [(3, 3, 3), (2, 5, 5)])
+    assert e.value.status == -2
+    with hj.Batch("f32", [(4, 4, 4), (5, 5, 5)]) as b:
+        with pytest.raises(hj.HJError) as e:
+            b.sweep(1, 0.8)
+        assert e.value.status == -6
+        with pytest.raises(hj.HJError):
+            b.config = hj.Config.make(kernel=0, bj=4, vec=1, ichunk=4, nontemporal=0, use_graph=1,
+                                      xcd_remap=0, persistent=0)
+        with pytest.raises(ValueError):
+            b.upload(1, "p", np.zeros((4, 4, 4)))

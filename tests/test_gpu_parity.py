@@ -1,0 +1,218 @@
+"""GPU parity: the HIP path against the CPU oracle on the same seeded inputs.
+
+FP64 fields must be bitwise equal (same evaluation order, no contraction),
+FP64 gosa within 1e-10 relative, FP32 fields within 1e-5 relative of the
+FP64 oracle. Shapes cover several tiles in every direction, ragged tails in
+k, j and i, single-cell interiors and random bnd masks.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2002_12115_amd import hj, inputs
+from _hjtest import (F32_FIELD_RTOL, F64_GOSA_RTOL, cfg, cfg_id, f32_configs, f64_configs,
+                     field_err, gosa_err, gpu_run, oracle_run, say)
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(3, 3, 3), (3, 4, 5), (5, 3, 4), (34, 34, 66), (19, 23, 37), (7, 9, 130),
+          (6, 5, 259), (40, 17, 67), (4, 70, 3)]
+
+_oracle_cache = {}
+
+
+def oracle_cached(shape, n_iter, seed=2002, bnd_mode=0):
+    key = (shape, n_iter, seed, bnd_mode)
+    if key not in _oracle_cache:
+        _oracle_cache[key] = oracle_run(shape, n_iter, seed=seed, bnd_mode=bnd_mode)
+    return _oracle_cache[key]
+
+
+@pytest.mark.parametrize("c", f64_configs(), ids=cfg_id)
+def test_f64_bitwise_all_shapes(c):
+    for shape in SHAPES:
+        for bnd_mode in (0, 1):
+            n = 7
+            say("f64", cfg_id(c), shape, "bnd_mode", bnd_mode)
+            p, hist, _ = gpu_run(shape, "f64", n, cfg=c, bnd_mode=bnd_mode)
+            pref, href = oracle_cached(shape, n, bnd_mode=bnd_mode)
+            assert np.array_equal(p, pref), (shape, bnd_mode, field_err(p, pref))
+            assert gosa_err(hist, href) <= F64_GOSA_RTOL, (shape, hist, href)
+
+
+@pytest.mark.parametrize("c", f32_configs(), ids=cfg_id)
+def test_f32_within_tolerance_all_shapes(c):
+    for shape in SHAPES:
+        n = 7
+        say("f32", cfg_id(c), shape)
+        p, hist, _ = gpu_run(shape, "f32", n, cfg=c)
+        pref, href = oracle_cached(shape, n)
+        assert field_err(p, pref) <= F32_FIELD_RTOL, (shape, field_err(p, pref))
+        assert np.all(np.isfinite(hist)) and gosa_err(hist, href) < 1e-3
+
+
+def test_f32_configs_agree_bitwise():
+    shape = (19, 23, 137)
+    f = inputs.fields(1, shape)
+    ref = None
+    for c in f32_configs():
+        say("f32 agree", cfg_id(c))
+        p, hist, _ = gpu_run(shape, "f32", 5, cfg=c, arrays=f)
+        if ref is None:
+            ref = (p, hist)
+        else:
+            assert np.array_equal(p, ref[0]), cfg_id(c)
+            assert gosa_err(hist, ref[1]) < 1e-12
+
+
+def test_small_f64_workload_50_iterations():
+    w = inputs.WORKLOADS["small_f64"]
+    say("small_f64 default config")
+    p, hist, _ = gpu_run(w.shape, "f64", w.iters, omega=w.omega, seed=w.seed)
+    pref, href = oracle_run(w.shape, w.iters, omega=w.omega, seed=w.seed)
+    assert np.array_equal(p, pref)
+    assert gosa_err(hist, href) <= F64_GOSA_RTOL
+    assert np.all(np.diff(hist) < 0)   # monotone decrease on this operator
+
+
+@pytest.mark.parametrize("seed", [2002, 1, 7])
+def test_seeds_and_torch_vs_library_memory(seed):
+    shape = (21, 18, 70)
+    pref, href = oracle_run(shape, 9, seed=seed)
+    for use_torch in (True, False):
+        say("seed", seed, "use_torch", use_torch)
+        p, hist, _ = gpu_run(shape, "f64", 9, seed=seed, use_torch=use_torch)
+        assert np.array_equal(p, pref)
+        assert gosa_err(hist, href) <= F64_GOSA_RTOL
+
+
+def test_residual_matches_oracle_and_history():
+    shape = (17, 20, 45)
+    f = inputs.fields(7, shape)
+    for dtype in ("f64", "f32"):
+        say("residual", dtype)
+        with hj.Solver(dtype, shape) as s:
+            s.upload_all(f)
+            g0 = s.residual()
+            ref0 = oracle.residual(f)
+            tol = 1e-12 if dtype == "f64" else 1e-4
+            assert abs(g0 - ref0) <= tol * ref0
+            s.sweep(4, 0.8)
+            assert s.gosa_history[0] == pytest.approx(g0, rel=1e-12)
+            g4 = s.residual()
+            p4, _, _ = oracle.sweep(f, 4, 0.8)
+            ref4 = oracle.residual(dict(f, p=p4))
+            assert abs(g4 - ref4) <= tol * ref4
+            # one more sweep: its history entry is this residual
+            s.sweep(1, 0.8)
+            assert s.gosa_history[0] == pytest.approx(g4, rel=1e-12)
+
+
+def test_graph_replays_match_eager():
+    shape = (30, 33, 100)
+    f = inputs.fields(2002, shape)
+    for dtype in ("f64", "f32"):
+        res = {}
+        for graph in (0, 1):
+            say("graph", graph, dtype)
+            with hj.Solver(dtype, shape) as s:
+                s.set(use_graph=graph)
+                s.upload_all(f)
+                hs, ps = [], []
+                for rep in range(4):         # replays with eager host work between them
+                    s.sweep(6, 0.8)
+                    hs.append(s.gosa_history.copy())
+                    ps.append(s.download("p"))
+                    _ = s.residual()
+                res[graph] = (hs, ps)
+        for a, b in zip(res[0][0], res[1][0]):
+            assert np.array_equal(a, b)
+        for a, b in zip(res[0][1], res[1][1]):
+            assert np.array_equal(a, b)
+
+
+def test_sweep_in_pieces_equals_one_call():
+    shape = (12, 13, 70)
+    f = inputs.fields(1, shape)
+    with hj.Solver("f64", shape) as s:
+        s.upload_all(f)
+        h = []
+        for n in (1, 2, 3, 5):
+            say("pieces", n)
+            s.sweep(n, 0.8)
+            h.extend(s.gosa_history)
+        p_pieces = s.download("p")
+        assert np.array_equal(s.download("wrk2"), p_pieces)
+    pref, href = oracle_run(shape, 11, seed=1)
+    assert np.array_equal(p_pieces, pref)
+    assert gosa_err(h, href) <= F64_GOSA_RTOL
+
+
+def test_run_to_run_deterministic():
+    shape = (50, 40, 300)
+    f = inputs.fields(7, shape)
+    outs = []
+    for _ in range(3):
+        say("determinism")
+        p, hist, _ = gpu_run(shape, "f64", 5, arrays=f)
+        outs.append((p, hist))
+    for p, hist in outs[1:]:
+        assert np.array_equal(p, outs[0][0])
+        assert np.array_equal(hist, outs[0][1])   # fixed-order reduction: same bits
+
+
+def test_download_coefficients_round_trip():
+    shape = (6, 7, 9)
+    f = inputs.fields(2002, shape)
+    with hj.Solver("f32", shape) as s:
+        s.upload_all(f)
+        for n in inputs.INPUTS:
+            assert np.array_equal(s.download(n), f[n].astype(np.float32)), n
+
+
+def test_error_paths():
+    shape = (5, 6, 7)
+    f = inputs.fields(1, shape)
+    with hj.Solver("f64", shape) as s:
+        with pytest.raises(hj.HJError) as e:
+            s.sweep(1, 0.8)
+        assert e.value.status == -6            # not every input uploaded
+        with pytest.raises(hj.HJError) as e:
+            s.upload("wrk2", f["p"])
+        assert e.value.status == -1
+        with pytest.raises(hj.HJError) as e:
+            s.config = cfg(bj=3)
+        assert e.value.status == -1
+        with pytest.raises(hj.HJError) as e:
+            s.config = cfg(vec=4)              # vec 4 is FP32 only
+        assert e.value.status == -1
+        s.upload_all(f)
+        with pytest.raises(hj.HJError):
+            s.sweep(-1, 0.8)
+        p0 = s.download("p")
+        s.sweep(0, 0.8)                        # no-op
+        assert np.array_equal(s.download("p"), p0)
+        h = s._h
+    lib = hj.load()
+    assert lib.hj_sweep(h, 1, 0.8, None, None) == -7     # destroyed handle
+
+
+def test_autotune_restores_state_and_keeps_parity():
+    shape = (40, 36, 140)
+    f = inputs.fields(2002, shape)
+    for dtype in ("f64", "f32"):
+        with hj.Solver(dtype, shape) as s:
+            s.upload_all(f)
+            s.sweep(3, 0.8)
+            before = s.download("p")
+            say("autotune", dtype)
+            best, ms = s.autotune(n_sweeps=2, repeats=1)
+            assert ms > 0
+            assert np.array_equal(s.download("p"), before)
+            s.sweep(4, 0.8)
+            p = s.download("p")
+        pref, _ = oracle_run(shape, 7, seed=2002)
+        if dtype == "f64":
+            assert np.array_equal(p, pref), best
+        else:
+            assert field_err(p, pref) <= F32_FIELD_RTOL
