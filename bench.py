@@ -31,6 +31,7 @@ PEAK_HBM_GBPS = 8000.0          # MI355X HBM3E, vendor figure
 KERNEL_SOURCES = ["paper_2002_12115_amd/csrc/sweep_kernels.hpp", "paper_2002_12115_amd/csrc/sweep_types.hpp",
                   "paper_2002_12115_amd/csrc/hj_kernels.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+TUNE_CACHE = os.path.join(ROOT, "paper_2002_12115_amd", "tune_cache.txt")
 
 
 def log(*a):
@@ -43,6 +44,34 @@ def kernel_hash() -> str:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def device_arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def cache_has(kind: str, dtype: str, key: str) -> bool:
+    """Whether the tuning cache (HJ_TUNE_CACHE) holds this problem."""
+    path = os.environ.get("HJ_TUNE_CACHE")
+    if not path or not os.path.exists(path):
+        return False
+    arch = device_arch()
+    with open(path) as f:
+        for line in f:
+            t = line.split()
+            if len(t) >= 4 and t[:4] == [kind, arch, dtype, key]:
+                return True
+    return False
+
+
+def batch_key(shapes) -> str:
+    h = 1469598103934665603
+    for sh in shapes:
+        for d in sh:
+            h ^= d & 0xFFFFFFFF
+            h = (h * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return "n%d-%016x" % (len(shapes), h)
 
 
 def interior(shape):
@@ -107,9 +136,12 @@ def run_single(w, args, hj, inputs):
     upload_s = time.perf_counter() - t0
     log("uploaded in %.2f s" % upload_s)
     tuned_ms = None
-    if args.tune:
+    key = "%dx%dx%d" % tuple(w.shape)
+    if args.retune or not cache_has("solve", w.dtype, key):
         c, tuned_ms = s.autotune(n_sweeps=args.tune_sweeps, repeats=3)
         log("autotuned:", c, "%.3f ms per %d sweeps" % (tuned_ms, args.tune_sweeps))
+    else:
+        log("configuration from the tuning cache:", s.config)
     cfg = s.config.as_dict()
 
     # accuracy check on the first solve from the initial field
@@ -140,8 +172,20 @@ def run_single(w, args, hj, inputs):
     avg_launch_ms = kernel_ms / launches
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     traffic = load_traffic(w.name, cfg)
+    ceilings = None
+    if args.ceilings:
+        # the library's probes on this GPU: a plain copy, and 13 reads + 1 write
+        # per cell over these very arrays (the sweep's traffic without its stencil)
+        nb = 2 << 30
+        hj.copy_probe(nb)
+        copy_ms = min(hj.copy_probe(nb) for _ in range(3))
+        sv = 2 if w.dtype == "f64" else 4
+        st_ms = min(s.stream_probe(sv, ich, 10) for ich in (2, 4, 8))
+        ceilings = {"copy_gbps": 2 * nb / copy_ms / 1e6,
+                    "stream13r1w_gbps": bytes_per_launch / st_ms / 1e6}
+        ceilings["frac_of_stream13r1w"] = achieved / ceilings["stream13r1w_gbps"]
     res = {
-        "glups": glups, "ms_per_step": wall * 1e3 / args.steps, "wall_s": wall,
+        "glups": glups, "ms_per_step": wall * 1e3 / args.steps, "wall_s": wall, "ceilings": ceilings,
         "hbm_gbps_alg": achieved, "frac_peak": achieved / PEAK_HBM_GBPS,
         "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_launch, "launches": launches,
         "upload_s": upload_s, "pcie_inclusive_glups": updates / (wall + upload_s) / 1e9,
@@ -203,9 +247,11 @@ def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune
         b = hj.Batch(dtype, shapes)
         for t, (sh, sd) in enumerate(zip(shapes, seeds)):
             b.upload_all(t, inputs.fields(sd, sh))
-        if tune:
+        if tune or not cache_has("batch", dtype, batch_key(shapes)):
             c, ms = b.autotune(n_sweeps=5, repeats=3)
             log("batch autotuned", dtype, c, ms)
+        else:
+            log("batch configuration from the tuning cache:", dtype, b.config)
         b.sweep(2, w.omega)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -247,13 +293,18 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="medium_f64")
-    ap.add_argument("--tune", action="store_true", help="autotune the kernel before timing")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune even when the tuning cache has this problem")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="also run the library's copy kernel over this many bytes (counter calibration)")
     ap.add_argument("--tune-sweeps", type=int, default=5)
     ap.add_argument("--check-iters", type=int, default=-1,
                     help="iterations compared with the oracle (default: all for small grids)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-ceilings", dest="ceilings", action="store_false",
+                    help="skip the copy and 13-read/1-write bandwidth probes")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: no oracle, no extras")
@@ -265,6 +316,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    os.environ.setdefault("HJ_TUNE_CACHE", TUNE_CACHE)
     import torch
     from paper_2002_12115_amd import hj, inputs
     if not torch.cuda.is_available():
@@ -278,10 +330,14 @@ def main():
         args.no_cpu_baseline = True
         args.no_extra = True
         args.check_iters = 0
+        args.ceilings = False
     if args.check_iters < 0:
         args.check_iters = w.iters if interior(w.shape) * w.iters <= 2e9 else 20
 
     res, arrays = run_single(w, args, hj, inputs)
+    if args.copy_probe:
+        ms = hj.copy_probe(args.copy_probe)
+        log("copy probe: %d bytes in %.3f ms = %.0f GB/s" % (args.copy_probe, ms, 2 * args.copy_probe / ms / 1e6))
     out = {
         "metric": METRIC,
         "value": res["glups"],
@@ -302,7 +358,7 @@ def main():
                      "unit": "GB/s", "frac": res["frac_peak"], "traffic": res["traffic"],
                      "kernel": "march_kernel" if res["config"]["kernel"] == 1 else "direct_kernel",
                      "bytes_per_launch": res["bytes_per_launch"],
-                     "avg_launch_ms": res["avg_launch_ms"]},
+                     "avg_launch_ms": res["avg_launch_ms"], "measured_ceilings": res["ceilings"]},
         "hbm_gbps_alg": res["hbm_gbps_alg"],
         "accuracy": res["accuracy"],
         "upload_s": res["upload_s"],
@@ -316,9 +372,9 @@ def main():
         log("transfer contrast...")
         extra["roundtrip_p_every_iteration"] = run_transfer_contrast(w, args, hj, inputs, arrays, 20)
         log("batch64 FP32 batched...")
-        extra["batch64_f32_batched"] = run_batch(args, hj, inputs, "f32", 100, False, args.tune)
+        extra["batch64_f32_batched"] = run_batch(args, hj, inputs, "f32", 100, False, args.retune)
         log("batch64 FP64 batched...")
-        extra["batch64_f64_batched"] = run_batch(args, hj, inputs, "f64", 100, False, args.tune)
+        extra["batch64_f64_batched"] = run_batch(args, hj, inputs, "f64", 100, False, args.retune)
         log("batch64 FP64 one launch per instance...")
         extra["batch64_f64_per_instance"] = run_batch(args, hj, inputs, "f64", 100, True, False)
         extra["batch64_f32_vs_f64_per_instance"] = (extra["batch64_f32_batched"]["glups"]

@@ -134,6 +134,10 @@ int hj_set_config(hj_solver h, const hj_config* cfg);
 /* Measure the candidate configurations on this handle's arrays and keep the
  * fastest one whose field is bitwise equal to the reference configuration's
  * after the same sweeps. The solve's state (p) is restored afterwards.
+ * With the environment variable HJ_TUNE_CACHE=<file>, the winner is recorded
+ * there (one text line per GPU architecture, dtype and shape), and handles
+ * created later for the same problem start from it. A candidate that fails
+ * to launch or to match the reference is never chosen.
  * n_sweeps per timing (>= 1), repeats (>= 1): median of repeats is scored.
  * best (nullable) receives the chosen configuration, best_ms its time. */
 int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double* best_ms);
@@ -174,6 +178,12 @@ const char* hj_last_error(void);
 /* Device time, in milliseconds, of the last hj_sweep / hj_batch_sweep on this
  * thread, measured with HIP events around the launched work. */
 double hj_last_sweep_ms(void);
+
+/* Bandwidth probe with the sweep's access pattern: n_rep launches that read
+ * the same 13 arrays and write the same one per interior cell, in the same
+ * layout, with no stencil; ms receives the average time per launch. The
+ * solve's state is unchanged. */
+int hj_stream_probe(hj_solver h, int vec, int ichunk, int n_rep, double* ms);
 
 /* Stream a plain device-to-device copy of `bytes` bytes between two device
  * buffers with the library's copy kernel (the bandwidth ceiling probe). */

@@ -125,16 +125,18 @@ int check_dtype(int dtype)
     return HJ_OK;
 }
 
+// Starting point before any tuning (the best measured family on MI355X:
+// non-temporal streams, 16-byte lanes, short i chunks; see the tune log).
 hj_config default_config(int dtype)
 {
     hj_config c;
     c.kernel = HJ_KERNEL_MARCH;
-    c.bj = 4;
-    c.vec = dtype == HJ_F64 ? 1 : 2;
-    c.ichunk = 16;
+    c.bj = dtype == HJ_F64 ? 4 : 8;
+    c.vec = dtype == HJ_F64 ? 2 : 4;
+    c.ichunk = 4;
     c.nontemporal = 1;
     c.use_graph = 1;
-    c.xcd_remap = 1;
+    c.xcd_remap = 0;
     c.persistent = 0;
     return c;
 }
@@ -281,10 +283,121 @@ void reg_del(void* h)
     g_registry.erase(h);
 }
 
+// Optional record of every autotuner measurement (HJ_TUNE_LOG=<csv path>).
+void tune_log(const char* what, int dtype, int nx, int ny, int nz, const hj_config& c, double ms,
+              const char* verdict)
+{
+    const char* path = getenv("HJ_TUNE_LOG");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s,%s,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%.6f,%s\n", what, dtype == HJ_F64 ? "f64" : "f32", nx,
+            ny, nz, c.kernel, c.bj, c.vec, c.ichunk, c.nontemporal, c.xcd_remap, c.persistent, ms, verdict);
+    fclose(f);
+}
+
 int median_index_sort(std::vector<float>& t)
 {
     std::sort(t.begin(), t.end());
     return (int)(t.size() / 2);
+}
+
+// ---- tuning cache ------------------------------------------------------------
+//
+// With HJ_TUNE_CACHE=<path>, every successful autotune records its winner as
+// one text line, and a new handle whose (kind, GPU architecture, dtype,
+// shape key) matches a line starts from that configuration:
+//   <kind> <arch> <f64|f32> <key> <kernel> <bj> <vec> <ichunk> <nt> <remap> <persistent> <ms>
+std::mutex g_cache_mu;
+
+const char* cache_path()
+{
+    const char* p = getenv("HJ_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+std::string device_arch()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    if (c != std::string::npos) a.resize(c);
+    return a.empty() ? "unknown" : a;
+}
+
+std::string solve_key(int nx, int ny, int nz)
+{
+    char b[64];
+    snprintf(b, sizeof b, "%dx%dx%d", nx, ny, nz);
+    return b;
+}
+
+std::string batch_key(const std::vector<Layout>& L)
+{
+    uint64_t h = 1469598103934665603ULL;  // FNV-1a over the instance shapes
+    for (const Layout& l : L)
+        for (int d : {l.nx, l.ny, l.nz}) {
+            h ^= (uint64_t)(uint32_t)d;
+            h *= 1099511628211ULL;
+        }
+    char b[64];
+    snprintf(b, sizeof b, "n%zu-%016llx", L.size(), (unsigned long long)h);
+    return b;
+}
+
+bool cache_get(const char* kind, int dtype, const std::string& key, hj_config& c)
+{
+    const char* path = cache_path();
+    if (!path) return false;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    const std::string arch = device_arch();
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char k[32], a[64], d[8], kk[128];
+        hj_config x = default_config(dtype);
+        double ms = 0;
+        if (sscanf(line, "%31s %63s %7s %127s %d %d %d %d %d %d %d %lf", k, a, d, kk, &x.kernel, &x.bj, &x.vec,
+                   &x.ichunk, &x.nontemporal, &x.xcd_remap, &x.persistent, &ms) != 12)
+            continue;
+        if (strcmp(k, kind) || arch != a || strcmp(d, dtype == HJ_F64 ? "f64" : "f32") || key != kk) continue;
+        c = x;
+        found = true;  // the last matching line wins
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_put(const char* kind, int dtype, const std::string& key, const hj_config& c, double ms)
+{
+    const char* path = cache_path();
+    if (!path) return;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    const std::string arch = device_arch();
+    const char* d = dtype == HJ_F64 ? "f64" : "f32";
+    std::vector<std::string> keep;
+    if (FILE* f = fopen(path, "r")) {
+        char line[512];
+        while (fgets(line, sizeof line, f)) {
+            char k[32], a[64], dd[8], kk[128];
+            if (sscanf(line, "%31s %63s %7s %127s", k, a, dd, kk) == 4 && !strcmp(k, kind) && arch == a &&
+                !strcmp(dd, d) && key == kk)
+                continue;  // replaced below
+            keep.emplace_back(line);
+        }
+        fclose(f);
+    }
+    FILE* f = fopen(path, "w");
+    if (!f) return;
+    for (const std::string& l : keep) fputs(l.c_str(), f);
+    fprintf(f, "%s %s %s %s %d %d %d %d %d %d %d %.6f\n", kind, arch.c_str(), d, key.c_str(), c.kernel, c.bj,
+            c.vec, c.ichunk, c.nontemporal, c.xcd_remap, c.persistent, ms);
+    fclose(f);
 }
 
 }  // namespace
@@ -440,25 +553,106 @@ int solver_init(hj_solver* out, int dtype, int nx, int ny, int nz, void* dev_sla
 }
 
 // Host <-> device copies of one dense field.
-void copy_in(const Layout& L, char* field, const void* src, hipStream_t st)
+// Host <-> device copies of one dense field. They go through two pinned
+// staging buffers shared by the process, so the PCIe transfer of one chunk of
+// rows overlaps the host-side copy (or FP64 -> FP32 rounding) of the next.
+// Rows too long for a staging buffer take a direct pitched copy.
+struct Stager {
+    static constexpr size_t kBytes = 32u << 20;
+    std::mutex mu;
+    void* buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    void ensure()
+    {
+        for (int q = 0; q < 2; ++q) {
+            if (!buf[q]) HIPCHK(hipHostMalloc(&buf[q], kBytes, hipHostMallocDefault));
+            if (!ev[q]) HIPCHK(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
+        }
+    }
+};
+
+Stager& stager()
+{
+    static Stager* s = new Stager();  // lives until the process ends
+    return *s;
+}
+
+void round_rows(float* dst, const double* src, size_t n)
+{
+    for (size_t q = 0; q < n; ++q) dst[q] = (float)src[q];  // round to nearest even
+}
+
+// src holds nx*ny rows of nz values: doubles when src_f64, else the field's type.
+void copy_in(const Layout& L, char* field, const void* src, bool src_f64, hipStream_t st)
 {
     char* dst = field + (size_t)(L.A - 1) * L.esz;
-    HIPCHK(hipMemcpy2DAsync(dst, (size_t)L.P * L.esz, src, (size_t)L.nz * L.esz, (size_t)L.nz * L.esz,
-                            (size_t)L.nx * L.ny, hipMemcpyHostToDevice, st));
+    const size_t row = (size_t)L.nz * L.esz, pitch = (size_t)L.P * L.esz;
+    const size_t rows = (size_t)L.nx * L.ny;
+    const bool convert = src_f64 && L.esz == 4;
+    if (row > Stager::kBytes) {
+        std::vector<float> tmp;
+        const void* s = src;
+        if (convert) {
+            tmp.resize(rows * L.nz);
+            round_rows(tmp.data(), static_cast<const double*>(src), tmp.size());
+            s = tmp.data();
+        }
+        HIPCHK(hipMemcpy2DAsync(dst, pitch, s, row, row, rows, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return;
+    }
+    Stager& sg = stager();
+    std::lock_guard<std::mutex> lk(sg.mu);
+    sg.ensure();
+    const size_t chunk = Stager::kBytes / row;
+    bool used[2] = {false, false};
+    int b = 0;
+    for (size_t r0 = 0; r0 < rows; r0 += chunk, b ^= 1) {
+        const size_t n = std::min(chunk, rows - r0);
+        if (used[b]) HIPCHK(hipEventSynchronize(sg.ev[b]));
+        if (convert)
+            round_rows(static_cast<float*>(sg.buf[b]), static_cast<const double*>(src) + r0 * L.nz, n * L.nz);
+        else
+            memcpy(sg.buf[b], static_cast<const char*>(src) + r0 * row, n * row);
+        HIPCHK(hipMemcpy2DAsync(dst + r0 * pitch, pitch, sg.buf[b], row, row, n, hipMemcpyHostToDevice, st));
+        HIPCHK(hipEventRecord(sg.ev[b], st));
+        used[b] = true;
+    }
+    HIPCHK(hipStreamSynchronize(st));
 }
 
 void copy_out(const Layout& L, const char* field, void* dst, hipStream_t st)
 {
     const char* src = field + (size_t)(L.A - 1) * L.esz;
-    HIPCHK(hipMemcpy2DAsync(dst, (size_t)L.nz * L.esz, src, (size_t)L.P * L.esz, (size_t)L.nz * L.esz,
-                            (size_t)L.nx * L.ny, hipMemcpyDeviceToHost, st));
-}
-
-std::vector<float> to_f32(const double* src, size_t n)
-{
-    std::vector<float> v(n);
-    for (size_t q = 0; q < n; ++q) v[q] = (float)src[q];  // round to nearest even
-    return v;
+    const size_t row = (size_t)L.nz * L.esz, pitch = (size_t)L.P * L.esz;
+    const size_t rows = (size_t)L.nx * L.ny;
+    if (row > Stager::kBytes) {
+        HIPCHK(hipMemcpy2DAsync(dst, row, src, pitch, row, rows, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return;
+    }
+    Stager& sg = stager();
+    std::lock_guard<std::mutex> lk(sg.mu);
+    sg.ensure();
+    const size_t chunk = Stager::kBytes / row;
+    size_t prev_r0 = 0, prev_n = 0;
+    int b = 0;
+    for (size_t r0 = 0; r0 < rows; r0 += chunk, b ^= 1) {
+        const size_t n = std::min(chunk, rows - r0);
+        HIPCHK(hipMemcpy2DAsync(sg.buf[b], row, src + r0 * pitch, pitch, row, n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(sg.ev[b], st));
+        if (prev_n) {  // drain the other buffer while this chunk is in flight
+            HIPCHK(hipEventSynchronize(sg.ev[b ^ 1]));
+            memcpy(static_cast<char*>(dst) + prev_r0 * row, sg.buf[b ^ 1], prev_n * row);
+        }
+        prev_r0 = r0;
+        prev_n = n;
+    }
+    if (prev_n) {
+        HIPCHK(hipEventSynchronize(sg.ev[b ^ 1]));
+        memcpy(static_cast<char*>(dst) + prev_r0 * row, sg.buf[b ^ 1], prev_n * row);
+    }
+    HIPCHK(hipStreamSynchronize(st));
 }
 
 int validate_config(int dtype, const hj_config* c)
@@ -495,9 +689,9 @@ std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch)
             const long long jt = (ny - 2 + bj - 1) / bj;
             const long long base_tiles = kt * jt;
             std::vector<int> ich;
-            for (long long target : {512LL, 1024LL, 2048LL, 4096LL}) {
+            for (long long target : {1024LL, 2048LL, 4096LL, 8192LL, 16384LL}) {
                 long long nchunks = (target + base_tiles - 1) / base_tiles;
-                int c = (int)std::max<long long>(2, (ni + nchunks - 1) / nchunks);
+                int c = (int)std::max<long long>(1, (ni + nchunks - 1) / nchunks);
                 c = std::min(c, std::max(ni, 1));
                 if (std::find(ich.begin(), ich.end(), c) == ich.end()) ich.push_back(c);
             }
@@ -523,10 +717,22 @@ int default_ichunk(int dtype, const hj_config& c, int nx, int ny, int nz)
 {
     const long long kt = (nz - 2 + 64 * c.vec - 1) / (64 * c.vec);
     const long long jt = (ny - 2 + c.bj - 1) / c.bj;
-    const long long target = 2048;
+    const long long target = 4096;
     const long long nchunks = std::max<long long>(1, (target + kt * jt - 1) / (kt * jt));
     (void)dtype;
-    return (int)std::max<long long>(4, (nx - 2 + nchunks - 1) / nchunks);
+    return (int)std::max<long long>(1, (nx - 2 + nchunks - 1) / nchunks);
+}
+
+// Default configuration, or the tuning cache's entry for this problem.
+void apply_start_config(hj_solver h)
+{
+    h->cfg.ichunk = default_ichunk(h->dtype, h->cfg, h->L.nx, h->L.ny, h->L.nz);
+    hj_config c;
+    if (cache_get("solve", h->dtype, solve_key(h->L.nx, h->L.ny, h->L.nz), c) && config_supported(h->dtype, c)) {
+        c.use_graph = 1;
+        c.persistent = 0;
+        h->cfg = c;
+    }
 }
 
 }  // namespace
@@ -567,7 +773,7 @@ int hj_create(hj_solver* out, int dtype, int nx, int ny, int nz, void* stream)
 {
     return guarded([&]() -> int {
         const int rc = solver_init(out, dtype, nx, ny, nz, nullptr, 0, stream);
-        if (rc == HJ_OK) (*out)->cfg.ichunk = default_ichunk(dtype, (*out)->cfg, nx, ny, nz);
+        if (rc == HJ_OK) apply_start_config(*out);
         return rc;
     });
 }
@@ -578,12 +784,14 @@ int hj_attach(hj_solver* out, int dtype, int nx, int ny, int nz, void* device_sl
     if (!device_slab) return set_err(HJ_ERR_ARG, "device_slab is NULL");
     return guarded([&]() -> int {
         const int rc = solver_init(out, dtype, nx, ny, nz, device_slab, slab_bytes, stream);
-        if (rc == HJ_OK) (*out)->cfg.ichunk = default_ichunk(dtype, (*out)->cfg, nx, ny, nz);
+        if (rc == HJ_OK) apply_start_config(*out);
         return rc;
     });
 }
 
-int hj_upload(hj_solver h, int field, const void* src)
+namespace {
+
+int solver_upload(hj_solver h, int field, const void* src, bool src_f64)
 {
     if (int rc = check_solver(h)) return rc;
     if (!src) return set_err(HJ_ERR_ARG, "host_src is NULL");
@@ -591,28 +799,22 @@ int hj_upload(hj_solver h, int field, const void* src)
     if (field < 0 || field >= HJ_WRK2) return set_err(HJ_ERR_ARG, "field %d out of range", field);
     return guarded([&]() -> int {
         if (field == HJ_P) {
-            copy_in(h->L, h->field(HJ_P), src, h->stream);
-            copy_in(h->L, h->field(HJ_WRK2), src, h->stream);
+            copy_in(h->L, h->field(HJ_P), src, src_f64, h->stream);
+            copy_in(h->L, h->field(HJ_WRK2), src, src_f64, h->stream);
             h->parity = 0;
         } else {
-            copy_in(h->L, h->field(field), src, h->stream);
+            copy_in(h->L, h->field(field), src, src_f64, h->stream);
         }
-        HIPCHK(hipStreamSynchronize(h->stream));
         h->uploaded |= 1u << field;
         return HJ_OK;
     });
 }
 
-int hj_upload_f64(hj_solver h, int field, const double* src)
-{
-    if (int rc = check_solver(h)) return rc;
-    if (!src) return set_err(HJ_ERR_ARG, "host_src is NULL");
-    if (h->dtype == HJ_F64) return hj_upload(h, field, src);
-    return guarded([&]() -> int {
-        std::vector<float> v = to_f32(src, (size_t)h->L.nx * h->L.ny * h->L.nz);
-        return hj_upload(h, field, v.data());
-    });
-}
+}  // namespace
+
+int hj_upload(hj_solver h, int field, const void* src) { return solver_upload(h, field, src, false); }
+
+int hj_upload_f64(hj_solver h, int field, const double* src) { return solver_upload(h, field, src, true); }
 
 int hj_download(hj_solver h, int field, void* dst)
 {
@@ -623,7 +825,6 @@ int hj_download(hj_solver h, int field, void* dst)
         int q = field;
         if (field == HJ_P || field == HJ_WRK2) q = h->parity ? HJ_WRK2 : HJ_P;
         copy_out(h->L, h->field(q), dst, h->stream);
-        HIPCHK(hipStreamSynchronize(h->stream));
         return HJ_OK;
     });
 }
@@ -748,6 +949,7 @@ int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double*
                 h->run(n_sweeps, 0.8, out);
             } catch (const HipFail&) {
                 (void)hipGetLastError();
+                tune_log("solve", h->dtype, L.nx, L.ny, L.nz, c, INFINITY, "launch-failed");
                 continue;  // a candidate that does not launch scores as infinitely slow
             }
             const char* cur = h->field(h->parity ? HJ_WRK2 : HJ_P);
@@ -760,7 +962,10 @@ int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double*
                 HIPCHK(launch_diff(cur, ref.p, L.field_bytes, static_cast<unsigned long long*>(cnt.p), h->stream));
                 HIPCHK(hipMemcpyAsync(&bad, cnt.p, 8, hipMemcpyDeviceToHost, h->stream));
                 HIPCHK(hipStreamSynchronize(h->stream));
-                if (bad) continue;  // not bitwise equal to the reference: rejected
+                if (bad) {  // not bitwise equal to the reference: rejected
+                    tune_log("solve", h->dtype, L.nx, L.ny, L.nz, c, INFINITY, "parity-failed");
+                    continue;
+                }
             }
             if (ci == 0 && cands.size() > 1) continue;  // reference itself is not a contender
             std::vector<float> t;
@@ -774,6 +979,7 @@ int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double*
                 t.push_back(ms);
             }
             const double med = t[median_index_sort(t)];
+            tune_log("solve", h->dtype, L.nx, L.ny, L.nz, c, med, "ok");
             if (med < win_ms) {
                 win_ms = med;
                 win = c;
@@ -788,6 +994,7 @@ int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double*
         }
         win.use_graph = keep.use_graph;
         h->cfg = win;
+        cache_put("solve", h->dtype, solve_key(L.nx, L.ny, L.nz), win, win_ms);
         if (best) *best = win;
         if (best_ms) *best_ms = win_ms;
         return HJ_OK;
@@ -828,6 +1035,31 @@ int hj_destroy(hj_solver h)
     h->magic = 0;
     delete h;
     return HJ_OK;
+}
+
+int hj_stream_probe(hj_solver h, int vec, int ichunk, int n_rep, double* ms)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (n_rep < 1 || !ms) return set_err(HJ_ERR_ARG, "need n_rep >= 1 and ms");
+    if ((h->uploaded & kInputMask) != (unsigned)kInputMask)
+        return set_err(HJ_ERR_STATE, "not every input field is uploaded");
+    return guarded([&]() -> int {
+        // writes the interior of the ping-pong partner, which the next sweep
+        // overwrites before reading it: the solve's state is unchanged
+        auto go = [&](hipStream_t st) -> hipError_t {
+            if (h->dtype == HJ_F64) return launch_stream_probe<double>(h->grid<double>(h->parity), vec, ichunk, st);
+            return launch_stream_probe<float>(h->grid<float>(h->parity), vec, ichunk, st);
+        };
+        HIPCHK(go(h->stream));
+        HIPCHK(hipEventRecord(h->ev0, h->stream));
+        for (int r = 0; r < n_rep; ++r) HIPCHK(go(h->stream));
+        HIPCHK(hipEventRecord(h->ev1, h->stream));
+        HIPCHK(hipEventSynchronize(h->ev1));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, h->ev0, h->ev1));
+        *ms = t / n_rep;
+        return HJ_OK;
+    });
 }
 
 int hj_copy_probe(void* dst, const void* src, unsigned long long bytes, void* stream, double* ms)
@@ -1050,6 +1282,15 @@ int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* n
         }
         b->slab_bytes = total;
         b->cfg = batch_default(dtype);
+        {
+            hj_config c;
+            if (cache_get("batch", dtype, batch_key(b->L), c) && config_supported(dtype, c) &&
+                c.kernel == HJ_KERNEL_MARCH) {
+                c.use_graph = 1;
+                c.xcd_remap = 0;
+                b->cfg = c;
+            }
+        }
         try {
             HIPCHK(hipMalloc(reinterpret_cast<void**>(&b->slab), total));
             if (stream) {
@@ -1079,7 +1320,9 @@ int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* n
     });
 }
 
-int hj_batch_upload(hj_batch b, int inst, int field, const void* src)
+namespace {
+
+int batch_upload(hj_batch b, int inst, int field, const void* src, bool src_f64)
 {
     if (int rc = check_batch(b)) return rc;
     if (inst < 0 || inst >= b->n) return set_err(HJ_ERR_ARG, "instance %d out of range", inst);
@@ -1090,28 +1333,26 @@ int hj_batch_upload(hj_batch b, int inst, int field, const void* src)
         if (field == HJ_P) {
             // the pair shares one parity: keep the instance's current buffer
             // and its partner identical so any parity is valid
-            copy_in(b->L[inst], b->field(inst, HJ_P), src, b->stream);
-            copy_in(b->L[inst], b->field(inst, HJ_WRK2), src, b->stream);
+            copy_in(b->L[inst], b->field(inst, HJ_P), src, src_f64, b->stream);
+            copy_in(b->L[inst], b->field(inst, HJ_WRK2), src, src_f64, b->stream);
         } else {
-            copy_in(b->L[inst], b->field(inst, field), src, b->stream);
+            copy_in(b->L[inst], b->field(inst, field), src, src_f64, b->stream);
         }
-        HIPCHK(hipStreamSynchronize(b->stream));
         b->uploaded[inst] |= 1u << field;
         return HJ_OK;
     });
 }
 
+}  // namespace
+
+int hj_batch_upload(hj_batch b, int inst, int field, const void* src)
+{
+    return batch_upload(b, inst, field, src, false);
+}
+
 int hj_batch_upload_f64(hj_batch b, int inst, int field, const double* src)
 {
-    if (int rc = check_batch(b)) return rc;
-    if (inst < 0 || inst >= b->n) return set_err(HJ_ERR_ARG, "instance %d out of range", inst);
-    if (!src) return set_err(HJ_ERR_ARG, "host_src is NULL");
-    if (b->dtype == HJ_F64) return hj_batch_upload(b, inst, field, src);
-    return guarded([&]() -> int {
-        const Layout& l = b->L[inst];
-        std::vector<float> v = to_f32(src, (size_t)l.nx * l.ny * l.nz);
-        return hj_batch_upload(b, inst, field, v.data());
-    });
+    return batch_upload(b, inst, field, src, true);
 }
 
 int hj_batch_download(hj_batch b, int inst, int field, void* dst)
@@ -1124,7 +1365,6 @@ int hj_batch_download(hj_batch b, int inst, int field, void* dst)
         int q = field;
         if (field == HJ_P || field == HJ_WRK2) q = b->parity ? HJ_WRK2 : HJ_P;
         copy_out(b->L[inst], b->field(inst, q), dst, b->stream);
-        HIPCHK(hipStreamSynchronize(b->stream));
         return HJ_OK;
     });
 }
@@ -1249,6 +1489,7 @@ int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, do
                 b->run(n_sweeps, 0.8, out);
             } catch (const HipFail&) {
                 (void)hipGetLastError();
+                tune_log("batch", b->dtype, b->n, 0, 0, c, INFINITY, "launch-failed");
                 continue;
             }
             if (!have_ref) {
@@ -1260,7 +1501,10 @@ int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, do
                 HIPCHK(launch_diff(b->slab, ref.p, b->slab_bytes, static_cast<unsigned long long*>(cnt.p), b->stream));
                 HIPCHK(hipMemcpyAsync(&bad, cnt.p, 8, hipMemcpyDeviceToHost, b->stream));
                 HIPCHK(hipStreamSynchronize(b->stream));
-                if (bad) continue;
+                if (bad) {
+                    tune_log("batch", b->dtype, b->n, 0, 0, c, INFINITY, "parity-failed");
+                    continue;
+                }
             }
             if (ci == 0 && cands.size() > 1) continue;
             std::vector<float> t;
@@ -1274,6 +1518,7 @@ int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, do
                 t.push_back(ms);
             }
             const double med = t[median_index_sort(t)];
+            tune_log("batch", b->dtype, b->n, 0, 0, c, med, "ok");
             if (med < win_ms) {
                 win_ms = med;
                 win = c;
@@ -1289,6 +1534,7 @@ int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, do
         }
         win.use_graph = keep.use_graph;
         b->cfg = win;
+        cache_put("batch", b->dtype, batch_key(b->L), win, win_ms);
         if (best) *best = win;
         if (best_ms) *best_ms = win_ms;
         return HJ_OK;

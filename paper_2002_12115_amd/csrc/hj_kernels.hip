@@ -200,6 +200,30 @@ hipError_t launch_copy(void* dst, const void* src, unsigned long long bytes, hip
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_stream_probe(const Grid<T>& g, int vec, int ichunk, hipStream_t st)
+{
+    constexpr int BJ = 4;
+    if (ichunk < 1) return hipErrorInvalidValue;
+    const int V = (vec == 4 && sizeof(T) == 4) ? 4 : (vec == 2 ? 2 : 1);
+    const int kt_n = (g.nz - 2 + kWave * V - 1) / (kWave * V);
+    const int jt_n = (g.ny - 2 + BJ - 1) / BJ;
+    const long long nb = (long long)kt_n * jt_n * chunks(g.nx, ichunk);
+    if (nb <= 0 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (V == 4) {
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((stream_kernel<T, BJ, 4>), dim3((unsigned)nb), dim3(kWave * BJ), 0, st, g, ichunk, kt_n, jt_n);
+    } else if (V == 2) {
+        hipLaunchKernelGGL((stream_kernel<T, BJ, 2>), dim3((unsigned)nb), dim3(kWave * BJ), 0, st, g, ichunk, kt_n, jt_n);
+    } else {
+        hipLaunchKernelGGL((stream_kernel<T, BJ, 1>), dim3((unsigned)nb), dim3(kWave * BJ), 0, st, g, ichunk, kt_n, jt_n);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_stream_probe<double>(const Grid<double>&, int, int, hipStream_t);
+template hipError_t launch_stream_probe<float>(const Grid<float>&, int, int, hipStream_t);
+
 hipError_t launch_diff(const void* a, const void* b, unsigned long long bytes,
                        unsigned long long* count, hipStream_t st)
 {

@@ -48,6 +48,10 @@ hipError_t launch_finalize(const double* part, long long stride, int n, const in
 
 hipError_t launch_copy(void* dst, const void* src, unsigned long long bytes, hipStream_t st);
 
+// 13-read / 1-write streaming probe over the interior (bj 4, V = 1 or 4).
+template <typename T>
+hipError_t launch_stream_probe(const Grid<T>& g, int vec, int ichunk, hipStream_t st);
+
 hipError_t launch_diff(const void* a, const void* b, unsigned long long bytes,
                        unsigned long long* count, hipStream_t st);
 

@@ -444,6 +444,40 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
 
 // ---- bandwidth probe and helpers ------------------------------------------------
 
+// Streaming ceiling of the sweep's access pattern: the same 13 reads and one
+// write per interior cell, in the same tiles and layout, with no stencil.
+template <typename T, int BJ, int V>
+__global__ __launch_bounds__(kWave * BJ) void stream_kernel(Grid<T> g, int ichunk, int kt_n, int jt_n)
+{
+    const int L = blockIdx.x;
+    const int kt = L % kt_n;
+    const int jt = (L / kt_n) % jt_n;
+    const int ic = L / (kt_n * jt_n);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int k = 1 + kt * kWave * V + lane * V, j = 1 + jt * BJ + w;
+    if (j > g.ny - 2 || k > g.nz - 2) return;
+    const int ib = 1 + ic * ichunk;
+    int ie = ib + ichunk;
+    if (ie > g.nx - 1) ie = g.nx - 1;
+    for (int i = ib; i < ie; ++i) {
+        const long long o = (long long)i * g.S + (long long)j * g.P + k;
+        T acc[V], x[V];
+        vload<T, V, false>(g.src + o, acc);
+#pragma unroll
+        for (int q = 0; q < NCOEF; ++q) {
+            vload<T, V, true>(g.coef[q] + o, x);
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] = acc[v] + x[v];
+        }
+        if (k + V - 1 <= g.nz - 2) vstore<T, V, true>(g.dst + o, acc);
+        else {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (k + v <= g.nz - 2) g.dst[o + v] = acc[v];
+        }
+    }
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void copy_kernel(const u32x4* __restrict__ src,

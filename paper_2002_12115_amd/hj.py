@@ -99,6 +99,7 @@ def load() -> ctypes.CDLL:
         "hj_batch_autotune": [H, i32, i32, cp, dp],
         "hj_batch_destroy": [H],
         "hj_copy_probe": [vp, vp, u64, vp, dp],
+        "hj_stream_probe": [H, i32, i32, i32, dp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -228,6 +229,13 @@ class Solver:
 
     def sync(self) -> None:
         check(self.lib.hj_sync(self._h), "hj_sync")
+
+    def stream_probe(self, vec: int = 1, ichunk: int = 16, n_rep: int = 10) -> float:
+        """ms per launch of the 13-read/1-write streaming probe on these arrays."""
+        ms = ctypes.c_double()
+        check(self.lib.hj_stream_probe(self._h, int(vec), int(ichunk), int(n_rep), ctypes.byref(ms)),
+              "hj_stream_probe")
+        return float(ms.value)
 
     @property
     def stream(self) -> int:

@@ -1,0 +1,120 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (the tuning cache the benchmark reads, or the defaults when it has no
+entry). Grids the oracle can sweep are compared whole; the 514x514x1026
+grid is compared on sampled cells, each recomputed by the oracle on its own
+3x3x3 neighbourhood (drawn from the counter-based generator), plus
+properties that hold at any size."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2002_12115_amd import hj, inputs
+from _hjtest import F32_FIELD_RTOL, F64_GOSA_RTOL, field_err, gosa_err, say
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CACHE = os.path.join(ROOT, "paper_2002_12115_amd", "tune_cache.txt")
+
+
+@pytest.fixture(autouse=True)
+def bench_configuration(monkeypatch):
+    monkeypatch.setenv("HJ_TUNE_CACHE", CACHE)
+
+
+def test_medium_f64_full_solve_bitwise():
+    w = inputs.WORKLOADS["medium_f64"]
+    f = inputs.fields(w.seed, w.shape)
+    say("medium_f64 full", w.iters)
+    with hj.Solver("f64", w.shape) as s:
+        s.upload_all(f)
+        s.sweep(w.iters, w.omega)
+        p, hist, cfg = s.download("p"), s.gosa_history.copy(), s.config
+    pref, _, href = oracle.sweep(f, w.iters, w.omega, nthreads=oracle.max_threads())
+    assert np.array_equal(p, pref), cfg
+    assert gosa_err(hist, href) <= F64_GOSA_RTOL
+    assert np.all(np.diff(hist) < 0)
+
+
+def test_large_f32_full_grid():
+    w = inputs.WORKLOADS["large_f32"]
+    n = 20
+    f = inputs.fields(w.seed, w.shape)
+    say("large_f32 full grid", n)
+    with hj.Solver("f32", w.shape) as s:
+        s.upload_all(f)
+        s.sweep(n, w.omega)
+        p, hist = s.download("p"), s.gosa_history.copy()
+    pref, _, href = oracle.sweep(f, n, w.omega, nthreads=oracle.max_threads())
+    assert field_err(p, pref) <= F32_FIELD_RTOL
+    # FP64 accumulation of FP32 residuals: close to the oracle before the FP32 floor
+    assert gosa_err(hist, href) < 1e-4
+
+
+def sample_cells(shape, m, rng):
+    nx, ny, nz = shape
+    pts = [np.stack([rng.integers(1, s - 1, m) for s in shape], 1)]
+    # faces, edges and corners of the interior, and the last k tile's tail
+    for i in (1, nx - 2):
+        for j in (1, ny - 2):
+            for k in (1, 2, nz - 3, nz - 2):
+                pts.append(np.array([[i, j, k]]))
+    pts.append(np.stack([rng.integers(1, nx - 1, 64), rng.integers(1, ny - 1, 64),
+                         np.full(64, nz - 2)], 1))
+    return np.concatenate(pts)
+
+
+def test_huge_f32_sampled_cells_and_properties():
+    w = inputs.WORKLOADS["huge_f32"]
+    shape = w.shape
+    say("huge_f32 upload")
+    with hj.Solver("f32", shape) as s:
+        for name in inputs.INPUTS:          # one field at a time: about 1 GiB each
+            s.upload(name, inputs.field(w.seed, name, shape, dtype=np.float32))
+        say("huge_f32 sweep 1")
+        s.sweep(1, w.omega)
+        p1 = s.download("p")
+        say("huge_f32 sweep 3 more")
+        s.sweep(3, w.omega)
+        hist = s.gosa_history.copy()
+        g_after = s.residual()
+    rng = np.random.default_rng(5)
+    cells = sample_cells(shape, 3000, rng)
+    nb = inputs.neighbourhood(w.seed, shape, cells, dtype=np.float32)
+    ref = np.empty(len(cells))
+    for q in range(len(cells)):
+        blk = {n: nb[n][q] for n in inputs.INPUTS}
+        ref[q] = oracle.sweep(blk, 1, w.omega)[0][1, 1, 1]
+    got = p1[cells[:, 0], cells[:, 1], cells[:, 2]].astype(np.float64)
+    assert np.abs(got - ref).max() <= F32_FIELD_RTOL * np.abs(ref).max()
+    # the shell is never written
+    p0 = inputs.field(w.seed, "p", shape, dtype=np.float32)
+    for sl in (np.s_[0], np.s_[-1], np.s_[:, 0], np.s_[:, -1], np.s_[:, :, 0], np.s_[:, :, -1]):
+        assert np.array_equal(p1[sl], p0[sl])
+    # gosa decreases (contraction) and the residual continues the history
+    assert np.all(np.isfinite(hist)) and np.all(np.diff(hist) < 0)
+    assert 0 < g_after < hist[-1]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch64_full_sizes(dtype):
+    w = inputs.WORKLOADS["batch64"]
+    shapes, seeds = inputs.batch_shapes(w.seed, w.batch)
+    n = 5
+    say("batch64", dtype)
+    arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
+    with hj.Batch(dtype, shapes) as b:
+        for t, a in enumerate(arrays):
+            b.upload_all(t, a)
+        b.sweep(n, w.omega)
+        hist = b.gosa_history.copy()
+        outs = [b.download(t) for t in range(len(shapes))]
+    for t, a in enumerate(arrays):
+        pref, _, href = oracle.sweep(a, n, w.omega, nthreads=oracle.max_threads())
+        if dtype == "f64":
+            assert np.array_equal(outs[t], pref), (t, shapes[t])
+            assert gosa_err(hist[:, t], href) <= F64_GOSA_RTOL
+        else:
+            assert field_err(outs[t], pref) <= F32_FIELD_RTOL, (t, shapes[t])

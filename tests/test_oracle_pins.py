@@ -314,3 +314,18 @@ def test_bad_arguments():
         oracle.sweep(f, -1, 0.8)
     p1, _, h = oracle.sweep(f, 0, 0.8)
     assert np.array_equal(p1, f["p"]) and h.size == 0
+
+
+def test_neighbourhood_blocks_reproduce_full_sweep():
+    """Sampled-cell checking of large grids: the oracle run on a cell's own
+    3x3x3 neighbourhood (values drawn at those positions) gives that cell's
+    value of a full-grid sweep."""
+    shape = (9, 11, 13)
+    f = inputs.fields(2002, shape)
+    p1, _, _ = oracle.sweep(f, 1, 0.8)
+    rng = np.random.default_rng(1)
+    cells = np.stack([rng.integers(1, s - 1, 40) for s in shape], 1)
+    nb = inputs.neighbourhood(2002, shape, cells)
+    for q, (i, j, k) in enumerate(cells):
+        blk = {n: nb[n][q] for n in inputs.INPUTS}
+        assert oracle.sweep(blk, 1, 0.8)[0][1, 1, 1] == p1[i, j, k]
