@@ -123,18 +123,47 @@ def accuracy(w, arrays, p_gpu, hist_gpu, iters: int):
             "field_bitwise": bool(np.array_equal(p_gpu.astype(np.float64), pref))}
 
 
-def run_single(w, args, hj, inputs):
-    """Time `steps` full solves of workload w; return (result dict, solver config)."""
-    dt = np.float64 if w.dtype == "f64" else np.float32
+def sampled_accuracy(w, inputs, p1, m: int = 2000):
+    """Field error after one sweep on sampled cells, each recomputed by the
+    oracle on its own 3x3x3 neighbourhood (grids too large to sweep on the host)."""
+    import oracle
+    rng = np.random.default_rng(11)
+    cells = np.stack([rng.integers(1, n - 1, m) for n in w.shape], 1)
+    nb = inputs.neighbourhood(w.seed, w.shape, cells,
+                              dtype=np.float64 if w.dtype == "f64" else np.float32)
+    ref = np.array([oracle.sweep({n: nb[n][q] for n in inputs.INPUTS}, 1, w.omega)[0][1, 1, 1]
+                    for q in range(m)])
+    got = p1[cells[:, 0], cells[:, 1], cells[:, 2]].astype(np.float64)
+    return {"field_rel_err": float(np.abs(got - ref).max() / np.abs(ref).max()),
+            "iters_checked": 1, "cells_checked": m}
+
+
+def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, keep_arrays: bool):
+    """Time `steps` full solves of workload w on resident arrays."""
+    n_int = interior(w.shape)
     log("workload", w.name, w.shape, w.dtype, "iters", w.iters)
     t0 = time.perf_counter()
-    arrays = inputs.fields(w.seed, w.shape)      # FP64 master copies (the oracle's inputs)
-    log("inputs generated in %.1f s" % (time.perf_counter() - t0))
     s = hj.Solver(w.dtype, w.shape)
-    t0 = time.perf_counter()
-    s.upload_all(arrays)
-    upload_s = time.perf_counter() - t0
-    log("uploaded in %.2f s" % upload_s)
+    arrays = None
+    if keep_arrays:
+        arrays = inputs.fields(w.seed, w.shape)   # FP64 master copies (the oracle's inputs)
+        gen_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        s.upload_all(arrays)
+        upload_s = time.perf_counter() - t0
+    else:
+        # one field at a time in the solver's dtype (RNE of the FP64 draws)
+        dt = np.float64 if w.dtype == "f64" else np.float32
+        gen_s = upload_s = 0.0
+        for name in inputs.INPUTS:
+            t1 = time.perf_counter()
+            a = inputs.field(w.seed, name, w.shape, dtype=dt)
+            t2 = time.perf_counter()
+            s.upload(name, a)
+            gen_s += t2 - t1
+            upload_s += time.perf_counter() - t2
+            del a
+    log("inputs generated in %.1f s, uploaded in %.2f s" % (gen_s, upload_s))
     tuned_ms = None
     key = "%dx%dx%d" % tuple(w.shape)
     if args.retune or not cache_has("solve", w.dtype, key):
@@ -144,30 +173,36 @@ def run_single(w, args, hj, inputs):
         log("configuration from the tuning cache:", s.config)
     cfg = s.config.as_dict()
 
-    # accuracy check on the first solve from the initial field
+    # accuracy of the first solve from the initial field
     acc = None
-    if args.check_iters:
-        n_chk = min(args.check_iters, w.iters)
+    if check_iters:
+        n_chk = min(check_iters, w.iters) if arrays is not None else 1
         s.sweep(n_chk, w.omega)
-        acc = accuracy(w, arrays, s.download("p"), s.gosa_history.copy(), n_chk)
+        if arrays is not None:
+            acc = accuracy(w, arrays, s.download("p"), s.gosa_history.copy(), n_chk)
+        else:
+            acc = sampled_accuracy(w, inputs, s.download("p"))
         log("accuracy", acc)
-        s.upload("p", arrays["p"])
+        if arrays is not None:
+            s.upload("p", arrays["p"])
+        else:
+            s.upload("p", inputs.field(w.seed, "p", w.shape,
+                                       dtype=np.float64 if w.dtype == "f64" else np.float32))
 
     import torch
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         s.sweep(w.iters, w.omega)
     torch.cuda.synchronize()
     kernel_ms = 0.0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         s.sweep(w.iters, w.omega)
         kernel_ms += s.last_ms          # HIP events on the solver's stream around each solve
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    n_int = interior(w.shape)
-    updates = n_int * w.iters * args.steps
+    updates = n_int * w.iters * steps
     glups = updates / wall / 1e9
-    launches = w.iters * args.steps
+    launches = w.iters * steps
     bytes_per_launch = 14 * esize(w.dtype) * n_int
     avg_launch_ms = kernel_ms / launches
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
@@ -185,12 +220,12 @@ def run_single(w, args, hj, inputs):
                     "stream13r1w_gbps": bytes_per_launch / st_ms / 1e6}
         ceilings["frac_of_stream13r1w"] = achieved / ceilings["stream13r1w_gbps"]
     res = {
-        "glups": glups, "ms_per_step": wall * 1e3 / args.steps, "wall_s": wall, "ceilings": ceilings,
+        "glups": glups, "ms_per_step": wall * 1e3 / steps, "wall_s": wall, "ceilings": ceilings,
         "hbm_gbps_alg": achieved, "frac_peak": achieved / PEAK_HBM_GBPS,
         "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_launch, "launches": launches,
         "upload_s": upload_s, "pcie_inclusive_glups": updates / (wall + upload_s) / 1e9,
         "traffic": traffic, "config": cfg, "tuned_ms": tuned_ms, "accuracy": acc,
-        "last_gosa": float(s.gosa_history[-1]),
+        "last_gosa": float(s.gosa_history[-1]), "steps": steps,
     }
     s.close()
     return res, arrays
@@ -334,7 +369,7 @@ def main():
     if args.check_iters < 0:
         args.check_iters = w.iters if interior(w.shape) * w.iters <= 2e9 else 20
 
-    res, arrays = run_single(w, args, hj, inputs)
+    res, arrays = run_single(w, args, hj, inputs, args.steps, args.warmup, args.check_iters, True)
     if args.copy_probe:
         ms = hj.copy_probe(args.copy_probe)
         log("copy probe: %d bytes in %.3f ms = %.0f GB/s" % (args.copy_probe, ms, 2 * args.copy_probe / ms / 1e6))
@@ -381,6 +416,14 @@ def main():
                                                     / extra["batch64_f64_per_instance"]["glups"])
         log("batch64 FP32 accuracy...")
         extra["batch64_f32_accuracy"] = batch_accuracy(hj, inputs, 10)
+        saved = args.ceilings
+        args.ceilings = False
+        for name, steps, chk, keep in (("large_f32", 3, 20, True), ("huge_f32", 2, 1, False)):
+            log(name, "...")
+            r, _ = run_single(inputs.WORKLOADS[name], args, hj, inputs, steps, 1, chk, keep)
+            extra[name] = {k: r[k] for k in ("glups", "ms_per_step", "hbm_gbps_alg", "frac_peak",
+                                             "avg_launch_ms", "config", "accuracy", "steps", "upload_s")}
+        args.ceilings = saved
         out["extra"] = extra
     print(json.dumps(out), flush=True)
 
