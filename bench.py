@@ -231,6 +231,28 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
     return res, arrays
 
 
+def tuner_comparison(w, hj, inputs, arrays):
+    """Exhaustive search against the paper's genetic search (population and
+    generations = gene length 10, Pc 0.9, Pm 0.05) on the same arrays."""
+    out = {}
+    for kind in ("exhaustive", "genetic"):
+        s = hj.Solver(w.dtype, w.shape)
+        s.upload_all(arrays)
+        os.environ["HJ_TUNE_CACHE"], saved = "", os.environ.get("HJ_TUNE_CACHE", "")
+        t0 = time.perf_counter()
+        if kind == "exhaustive":
+            c, ms = s.autotune(n_sweeps=5, repeats=3)
+            ev = None
+        else:
+            c, ms, ev = s.autotune_ga(10, 10, w.seed, 0.9, 0.05, n_sweeps=5, repeats=3)
+        dt = time.perf_counter() - t0
+        os.environ["HJ_TUNE_CACHE"] = saved
+        out[kind] = {"ms_per_sweep": ms / 5, "config": c.as_dict(), "evaluations": ev, "tune_s": dt,
+                     "hbm_gbps_alg": 14 * esize(w.dtype) * interior(w.shape) / (ms / 5) / 1e6}
+        s.close()
+    return out
+
+
 def run_transfer_contrast(w, args, hj, inputs, arrays, n_iter: int):
     """The same solve with a host round trip of p every iteration."""
     s = hj.Solver(w.dtype, w.shape)
@@ -404,6 +426,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, arrays, args.cpu_budget)
     if not args.no_extra:
         extra = {}
+        log("tuner comparison...")
+        extra["tuner_exhaustive_vs_genetic"] = tuner_comparison(w, hj, inputs, arrays)
         log("transfer contrast...")
         extra["roundtrip_p_every_iteration"] = run_transfer_contrast(w, args, hj, inputs, arrays, 20)
         log("batch64 FP32 batched...")

@@ -142,6 +142,35 @@ int hj_set_config(hj_solver h, const hj_config* cfg);
  * best (nullable) receives the chosen configuration, best_ms its time. */
 int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double* best_ms);
 
+/* The paper's genetic search (sections 4 and 5.1.2) as the search strategy
+ * of the autotuner, instead of trying every candidate. A gene is 10 bits
+ * (bit 0 kernel, bits 1-2 bj = 1,2,4,8, bits 3-4 vec = 1,2,4, bits 5-7 one of
+ * eight i-chunk lengths, bit 8 non-temporal, bit 9 XCD renumbering; see
+ * hj_gene_config). population and generations individuals are measured as
+ * by hj_autotune (same parity gate) with fitness (time)^(-1/2); a failed
+ * measurement or a gene that names no configuration counts as 1000 s.
+ * Roulette selection with elitism, one-point crossover with probability pc,
+ * per-bit mutation with probability pm (the paper uses 0.9 and 0.05, and a
+ * population and generation count no larger than the gene length). Random
+ * numbers come from a counter-based SplitMix64 stream of `seed`. Identical
+ * genes are measured once; evaluations (nullable) receives how many were.
+ * The winner is installed, recorded in the tuning cache and returned. */
+int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long long seed, double pc,
+                   double pm, int n_sweeps, int repeats, hj_config* best, double* best_ms,
+                   int* evaluations);
+
+/* The configuration a gene names for this problem (batch != 0: for a batch,
+ * where bit 9 selects the persistent grid). HJ_ERR_ARG if it names none. */
+int hj_gene_config(int dtype, int nx, int ny, int nz, int batch, unsigned gene, hj_config* out);
+
+/* The same genetic search with the time of every gene given by a table
+ * (time_of_gene[g] in seconds for g < 2^gene_bits, gene_bits <= 20). Host
+ * only: no GPU is used. history (nullable) receives the genes of every
+ * generation, [generations][population]. */
+int hj_ga_run(int gene_bits, int population, int generations, unsigned long long seed, double pc,
+              double pm, const double* time_of_gene, unsigned* best_gene, double* best_time,
+              unsigned* history, int* evaluations);
+
 /* Wait for all work queued on the handle's stream. */
 int hj_sync(hj_solver h);
 
@@ -168,6 +197,11 @@ int hj_batch_residual(hj_batch b, double* gosa);
 int hj_batch_get_config(hj_batch b, hj_config* out);
 int hj_batch_set_config(hj_batch b, const hj_config* cfg);
 int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, double* best_ms);
+/* Genetic search over the batch's configuration (as hj_autotune_ga; bit 9
+ * selects the persistent grid, the i-chunk is 2^(bits 5-7)). */
+int hj_batch_autotune_ga(hj_batch b, int population, int generations, unsigned long long seed, double pc,
+                         double pm, int n_sweeps, int repeats, hj_config* best, double* best_ms,
+                         int* evaluations);
 int hj_batch_destroy(hj_batch b);
 
 /* ---- diagnostics ---------------------------------------------------------- */

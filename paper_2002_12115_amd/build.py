@@ -12,8 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhj.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["hj_kernels.hip", "hj_api.hip"]
-HEADERS = ["sweep_types.hpp", "sweep_kernels.hpp", "hj_launch.hpp"]
+SOURCES = ["hj_kernels.hip", "hj_api.hip", "hj_ga.cpp"]
+HEADERS = ["sweep_types.hpp", "sweep_kernels.hpp", "hj_launch.hpp", "hj_ga.hpp"]
 
 # No FP contraction (the FP64 field must be bit-identical to a plain loop),
 # and no packed-FP32 instructions.

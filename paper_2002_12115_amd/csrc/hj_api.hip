@@ -16,12 +16,14 @@
 #include <cstdlib>
 #include <cstring>
 #include <exception>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <set>
 #include <string>
 #include <vector>
 
+#include "hj_ga.hpp"
 #include "hj_launch.hpp"
 
 using namespace hj;
@@ -398,6 +400,114 @@ void cache_put(const char* kind, int dtype, const std::string& key, const hj_con
     fprintf(f, "%s %s %s %s %d %d %d %d %d %d %d %.6f\n", kind, arch.c_str(), d, key.c_str(), c.kernel, c.bj,
             c.vec, c.ichunk, c.nontemporal, c.xcd_remap, c.persistent, ms);
     fclose(f);
+}
+
+// ---- autotuner measurement --------------------------------------------------
+
+// What the autotuner needs from a solve or a batch.
+struct TuneOps {
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::function<void(const hj_config&)> set;     // select a configuration (may throw)
+    std::function<void()> restore;                 // back to the saved state
+    std::function<void(int)> run;                  // enqueue n sweeps
+    std::function<std::pair<const void*, size_t>()> result;  // bytes the parity gate compares
+};
+
+// Times configurations on the caller's arrays. The first configuration
+// evaluated is the reference; every later one must leave a result bitwise
+// equal to it after the same sweeps, or it scores as failed (INFINITY).
+struct Evaluator {
+    TuneOps ops;
+    int n_sweeps = 1, repeats = 1;
+    const char* kind = "solve";
+    int dtype = HJ_F64, nx = 0, ny = 0, nz = 0;
+    DevBuf ref, cnt;
+    bool have_ref = false;
+
+    double eval(const hj_config& c)
+    {
+        try {
+            ops.set(c);
+            ops.restore();
+            ops.run(n_sweeps);
+        } catch (const HipFail&) {
+            (void)hipGetLastError();
+            tune_log(kind, dtype, nx, ny, nz, c, INFINITY, "launch-failed");
+            return INFINITY;  // a candidate that does not launch is never chosen
+        }
+        const std::pair<const void*, size_t> res = ops.result();
+        if (!have_ref) {
+            ref.ensure(res.second);
+            HIPCHK(hipMemcpyAsync(ref.p, res.first, res.second, hipMemcpyDeviceToDevice, ops.st));
+            have_ref = true;
+        } else {
+            unsigned long long bad = 0;
+            cnt.ensure(8);
+            HIPCHK(hipMemcpyAsync(cnt.p, &bad, 8, hipMemcpyHostToDevice, ops.st));
+            HIPCHK(launch_diff(res.first, ref.p, res.second, static_cast<unsigned long long*>(cnt.p), ops.st));
+            HIPCHK(hipMemcpyAsync(&bad, cnt.p, 8, hipMemcpyDeviceToHost, ops.st));
+            HIPCHK(hipStreamSynchronize(ops.st));
+            if (bad) {
+                tune_log(kind, dtype, nx, ny, nz, c, INFINITY, "parity-failed");
+                return INFINITY;
+            }
+        }
+        std::vector<float> t;
+        for (int r = 0; r < repeats; ++r) {
+            HIPCHK(hipEventRecord(ops.e0, ops.st));
+            ops.run(n_sweeps);
+            HIPCHK(hipEventRecord(ops.e1, ops.st));
+            HIPCHK(hipEventSynchronize(ops.e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ops.e0, ops.e1));
+            t.push_back(ms);
+        }
+        const double med = t[median_index_sort(t)];
+        tune_log(kind, dtype, nx, ny, nz, c, med, "ok");
+        return med;
+    }
+};
+
+// ---- the genetic search's gene ------------------------------------------------
+//
+// 10 bits: bit 0 kernel (0 direct, 1 march), bits 1-2 bj = 1,2,4,8, bits 3-4
+// vec = 1,2,4 (3 is not a configuration), bits 5-7 one of 8 i-chunk lengths,
+// bit 8 non-temporal streams, bit 9 XCD renumbering (single solve) or
+// persistent grid (batch). A gene that names no configuration scores as a
+// failed measurement.
+constexpr int kGeneBits = 10;
+
+// The 8 i-chunk lengths a gene can name for one grid: the chunk that gives
+// about 512, 1024, ..., 65536 workgroups.
+int gene_ichunk(int sel, const hj_config& c, int nx, int ny, int nz)
+{
+    const long long kt = (nz - 2 + 64 * c.vec - 1) / (64 * c.vec);
+    const long long jt = (ny - 2 + c.bj - 1) / c.bj;
+    const long long target = 512LL << sel;
+    const long long nchunks = std::max<long long>(1, (target + kt * jt - 1) / (kt * jt));
+    return (int)std::max<long long>(1, (nx - 2 + nchunks - 1) / nchunks);
+}
+
+bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_config& c)
+{
+    c = default_config(dtype);
+    c.kernel = (g & 1) ? HJ_KERNEL_MARCH : HJ_KERNEL_DIRECT;
+    c.bj = 1 << ((g >> 1) & 3);
+    const int vi = (g >> 3) & 3;
+    if (vi == 3) return false;
+    c.vec = 1 << vi;
+    const int sel = (g >> 5) & 7;
+    c.nontemporal = (g >> 8) & 1;
+    c.xcd_remap = batch ? 0 : (int)((g >> 9) & 1);
+    c.persistent = batch ? (int)((g >> 9) & 1) : 0;
+    if (c.kernel == HJ_KERNEL_DIRECT) {
+        if (batch || c.vec != 1 || sel != 0) return false;  // one spelling per direct configuration
+        c.ichunk = 1;
+    } else {
+        c.ichunk = batch ? (1 << sel) : gene_ichunk(sel, c, nx, ny, nz);
+    }
+    return config_supported(dtype, c);
 }
 
 }  // namespace
@@ -911,80 +1021,52 @@ int hj_set_config(hj_solver h, const hj_config* cfg)
     });
 }
 
-int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double* best_ms)
-{
-    if (int rc = check_solver(h)) return rc;
-    if (n_sweeps < 1 || repeats < 1) return set_err(HJ_ERR_ARG, "n_sweeps and repeats must be >= 1");
-    if ((h->uploaded & kInputMask) != (unsigned)kInputMask)
-        return set_err(HJ_ERR_STATE, "not every input field is uploaded");
-    return guarded([&]() -> int {
+namespace {
+
+// Tuning operations over a single solve: the saved state is the current
+// field, restored into both halves of the ping-pong pair.
+struct SolverTuning {
+    hj_solver h;
+    DevBuf save;
+    Evaluator ev;
+    hj_config keep;
+
+    SolverTuning(hj_solver hh, int n_sweeps, int repeats) : h(hh)
+    {
         const Layout& L = h->L;
-        const hj_config keep = h->cfg;
-        DevBuf save, ref, cnt;
+        keep = h->cfg;
         save.ensure(L.field_bytes);
-        ref.ensure(L.field_bytes);
-        cnt.ensure(8);
-        const int par0 = h->parity;
-        HIPCHK(hipMemcpyAsync(save.p, h->field(par0 ? HJ_WRK2 : HJ_P), L.field_bytes, hipMemcpyDeviceToDevice, h->stream));
-        auto restore = [&] {
-            HIPCHK(hipMemcpyAsync(h->field(HJ_P), save.p, L.field_bytes, hipMemcpyDeviceToDevice, h->stream));
-            HIPCHK(hipMemcpyAsync(h->field(HJ_WRK2), save.p, L.field_bytes, hipMemcpyDeviceToDevice, h->stream));
-            h->parity = 0;
-        };
-        std::vector<hj_config> cands = candidates(h->dtype, L.nx, L.ny, L.nz, false);
-        cands.insert(cands.begin(), reference_config(h->dtype));
-        hj_config win = keep;
-        double win_ms = INFINITY;
-        bool have_ref = false;
-        for (size_t ci = 0; ci < cands.size(); ++ci) {
-            hj_config c = cands[ci];
-            c.use_graph = 0;
+        HIPCHK(hipMemcpyAsync(save.p, h->field(h->parity ? HJ_WRK2 : HJ_P), L.field_bytes,
+                              hipMemcpyDeviceToDevice, h->stream));
+        ev.n_sweeps = n_sweeps;
+        ev.repeats = repeats;
+        ev.kind = "solve";
+        ev.dtype = h->dtype;
+        ev.nx = L.nx; ev.ny = L.ny; ev.nz = L.nz;
+        ev.ops.st = h->stream;
+        ev.ops.e0 = h->ev0;
+        ev.ops.e1 = h->ev1;
+        ev.ops.set = [this](const hj_config& c) {
             h->graphs.clear();
             h->cfg = c;
-            restore();
-            h->reserve(n_sweeps);
-            double* out = static_cast<double*>(h->gosa.p);
-            // one run for the parity gate (and warm-up)
-            try {
-                h->run(n_sweeps, 0.8, out);
-            } catch (const HipFail&) {
-                (void)hipGetLastError();
-                tune_log("solve", h->dtype, L.nx, L.ny, L.nz, c, INFINITY, "launch-failed");
-                continue;  // a candidate that does not launch scores as infinitely slow
-            }
-            const char* cur = h->field(h->parity ? HJ_WRK2 : HJ_P);
-            if (!have_ref) {
-                HIPCHK(hipMemcpyAsync(ref.p, cur, L.field_bytes, hipMemcpyDeviceToDevice, h->stream));
-                have_ref = true;
-            } else {
-                unsigned long long bad = 0;
-                HIPCHK(hipMemcpyAsync(cnt.p, &bad, 8, hipMemcpyHostToDevice, h->stream));
-                HIPCHK(launch_diff(cur, ref.p, L.field_bytes, static_cast<unsigned long long*>(cnt.p), h->stream));
-                HIPCHK(hipMemcpyAsync(&bad, cnt.p, 8, hipMemcpyDeviceToHost, h->stream));
-                HIPCHK(hipStreamSynchronize(h->stream));
-                if (bad) {  // not bitwise equal to the reference: rejected
-                    tune_log("solve", h->dtype, L.nx, L.ny, L.nz, c, INFINITY, "parity-failed");
-                    continue;
-                }
-            }
-            if (ci == 0 && cands.size() > 1) continue;  // reference itself is not a contender
-            std::vector<float> t;
-            for (int r = 0; r < repeats; ++r) {
-                HIPCHK(hipEventRecord(h->ev0, h->stream));
-                h->run(n_sweeps, 0.8, out);
-                HIPCHK(hipEventRecord(h->ev1, h->stream));
-                HIPCHK(hipEventSynchronize(h->ev1));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-                t.push_back(ms);
-            }
-            const double med = t[median_index_sort(t)];
-            tune_log("solve", h->dtype, L.nx, L.ny, L.nz, c, med, "ok");
-            if (med < win_ms) {
-                win_ms = med;
-                win = c;
-            }
-        }
+            h->cfg.use_graph = 0;
+            h->reserve(ev.n_sweeps);
+        };
+        ev.ops.restore = [this] { restore(); };
+        ev.ops.run = [this](int n) { h->run(n, 0.8, static_cast<double*>(h->gosa.p)); };
+        ev.ops.result = [this] {
+            return std::make_pair((const void*)h->field(h->parity ? HJ_WRK2 : HJ_P), h->L.field_bytes);
+        };
+    }
+    void restore()
+    {
+        HIPCHK(hipMemcpyAsync(h->field(HJ_P), save.p, h->L.field_bytes, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->field(HJ_WRK2), save.p, h->L.field_bytes, hipMemcpyDeviceToDevice, h->stream));
+        h->parity = 0;
+    }
+    // Put the state back and install the winner (or the old configuration).
+    int finish(const hj_config& win, double win_ms, hj_config* best, double* best_ms)
+    {
         restore();
         HIPCHK(hipStreamSynchronize(h->stream));
         h->graphs.clear();
@@ -992,12 +1074,68 @@ int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double*
             h->cfg = keep;
             return set_err(HJ_ERR_TUNE, "no candidate configuration passed");
         }
-        win.use_graph = keep.use_graph;
         h->cfg = win;
-        cache_put("solve", h->dtype, solve_key(L.nx, L.ny, L.nz), win, win_ms);
-        if (best) *best = win;
+        h->cfg.use_graph = keep.use_graph;
+        cache_put("solve", h->dtype, solve_key(h->L.nx, h->L.ny, h->L.nz), h->cfg, win_ms);
+        if (best) *best = h->cfg;
         if (best_ms) *best_ms = win_ms;
         return HJ_OK;
+    }
+};
+
+int solver_tunable(hj_solver h, int n_sweeps, int repeats)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (n_sweeps < 1 || repeats < 1) return set_err(HJ_ERR_ARG, "n_sweeps and repeats must be >= 1");
+    if ((h->uploaded & kInputMask) != (unsigned)kInputMask)
+        return set_err(HJ_ERR_STATE, "not every input field is uploaded");
+    return HJ_OK;
+}
+
+}  // namespace
+
+int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double* best_ms)
+{
+    if (int rc = solver_tunable(h, n_sweeps, repeats)) return rc;
+    return guarded([&]() -> int {
+        SolverTuning tu(h, n_sweeps, repeats);
+        tu.ev.eval(reference_config(h->dtype));  // the parity reference (also a contender below)
+        hj_config win = tu.keep;
+        double win_ms = INFINITY;
+        for (const hj_config& c : candidates(h->dtype, h->L.nx, h->L.ny, h->L.nz, false)) {
+            const double ms = tu.ev.eval(c);
+            if (ms < win_ms) {
+                win_ms = ms;
+                win = c;
+            }
+        }
+        return tu.finish(win, win_ms, best, best_ms);
+    });
+}
+
+int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long long seed, double pc,
+                   double pm, int n_sweeps, int repeats, hj_config* best, double* best_ms, int* evaluations)
+{
+    if (int rc = solver_tunable(h, n_sweeps, repeats)) return rc;
+    if (population < 1 || generations < 1 || !(pc >= 0.0 && pc <= 1.0) || !(pm >= 0.0 && pm <= 1.0))
+        return set_err(HJ_ERR_ARG, "need population, generations >= 1 and 0 <= pc, pm <= 1");
+    return guarded([&]() -> int {
+        SolverTuning tu(h, n_sweeps, repeats);
+        tu.ev.eval(reference_config(h->dtype));
+        const Layout& L = h->L;
+        auto time_of = [&](uint32_t g) -> double {
+            hj_config c;
+            if (!decode_gene(g, h->dtype, L.nx, L.ny, L.nz, false, c)) return hjga::kFailTime;
+            const double ms = tu.ev.eval(c);
+            return std::isfinite(ms) ? ms * 1e-3 : hjga::kFailTime;
+        };
+        const hjga::Result r = hjga::run(kGeneBits, population, generations, seed, pc, pm, time_of);
+        hj_config win = tu.keep;
+        double win_ms = INFINITY;
+        if (r.best_time < hjga::kFailTime && decode_gene(r.best_gene, h->dtype, L.nx, L.ny, L.nz, false, win))
+            win_ms = r.best_time * 1e3;
+        if (evaluations) *evaluations = r.evaluations;
+        return tu.finish(win, win_ms, best, best_ms);
     });
 }
 
@@ -1436,94 +1574,46 @@ int hj_batch_set_config(hj_batch b, const hj_config* cfg)
     });
 }
 
-int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, double* best_ms)
-{
-    if (int rc = check_batch(b)) return rc;
-    if (n_sweeps < 1 || repeats < 1) return set_err(HJ_ERR_ARG, "n_sweeps and repeats must be >= 1");
-    if (!b->all_uploaded()) return set_err(HJ_ERR_STATE, "not every input field of every instance is uploaded");
-    return guarded([&]() -> int {
-        const hj_config keep = b->cfg;
-        DevBuf save, ref, cnt;
+namespace {
+
+// Tuning operations over a batch: the saved state is the whole slab.
+struct BatchTuning {
+    hj_batch b;
+    DevBuf save;
+    Evaluator ev;
+    hj_config keep;
+    int par0;
+
+    BatchTuning(hj_batch bb, int n_sweeps, int repeats) : b(bb)
+    {
+        keep = b->cfg;
+        par0 = b->parity;
         save.ensure(b->slab_bytes);
-        ref.ensure(b->slab_bytes);
-        cnt.ensure(8);
-        const int par0 = b->parity;
         HIPCHK(hipMemcpyAsync(save.p, b->slab, b->slab_bytes, hipMemcpyDeviceToDevice, b->stream));
-        auto restore = [&] {
-            HIPCHK(hipMemcpyAsync(b->slab, save.p, b->slab_bytes, hipMemcpyDeviceToDevice, b->stream));
-            b->parity = par0;
-        };
-        // the biggest instance shapes the candidate list
-        int mx = 0;
-        for (int t = 1; t < b->n; ++t)
-            if ((long long)b->L[t].nx * b->L[t].ny * b->L[t].nz > (long long)b->L[mx].nx * b->L[mx].ny * b->L[mx].nz) mx = t;
-        long long cells = 0;
-        for (auto& l : b->L) cells += (long long)(l.nx - 2) * (l.ny - 2) * (l.nz - 2);
-        std::vector<hj_config> cands;
-        const int vmax = b->dtype == HJ_F64 ? 2 : 4;
-        for (int bj : {1, 2, 4, 8})
-            for (int v = 1; v <= vmax; v *= 2)
-                for (int ich : {4, 8, 16, 32})
-                    for (int nt : {0, 1})
-                        for (int per : {0, 1}) {
-                            hj_config c = batch_default(b->dtype);
-                            c.bj = bj; c.vec = v; c.ichunk = ich; c.nontemporal = nt; c.persistent = per;
-                            if (config_supported(b->dtype, c)) cands.push_back(c);
-                        }
-        (void)cells;
-        hj_config refc = batch_default(b->dtype);
-        refc.nontemporal = 0;
-        cands.insert(cands.begin(), refc);
-        hj_config win = keep;
-        double win_ms = INFINITY;
-        bool have_ref = false;
-        for (size_t ci = 0; ci < cands.size(); ++ci) {
-            hj_config c = cands[ci];
-            c.use_graph = 1;
+        ev.n_sweeps = n_sweeps;
+        ev.repeats = repeats;
+        ev.kind = "batch";
+        ev.dtype = b->dtype;
+        ev.nx = b->n;
+        ev.ops.st = b->stream;
+        ev.ops.e0 = b->ev0;
+        ev.ops.e1 = b->ev1;
+        ev.ops.set = [this](const hj_config& c) {
             b->cfg = c;
-            restore();
-            double* out = nullptr;
-            try {
-                b->reserve(n_sweeps);
-                out = static_cast<double*>(b->gosa.p);
-                b->run(n_sweeps, 0.8, out);
-            } catch (const HipFail&) {
-                (void)hipGetLastError();
-                tune_log("batch", b->dtype, b->n, 0, 0, c, INFINITY, "launch-failed");
-                continue;
-            }
-            if (!have_ref) {
-                HIPCHK(hipMemcpyAsync(ref.p, b->slab, b->slab_bytes, hipMemcpyDeviceToDevice, b->stream));
-                have_ref = true;
-            } else {
-                unsigned long long bad = 0;
-                HIPCHK(hipMemcpyAsync(cnt.p, &bad, 8, hipMemcpyHostToDevice, b->stream));
-                HIPCHK(launch_diff(b->slab, ref.p, b->slab_bytes, static_cast<unsigned long long*>(cnt.p), b->stream));
-                HIPCHK(hipMemcpyAsync(&bad, cnt.p, 8, hipMemcpyDeviceToHost, b->stream));
-                HIPCHK(hipStreamSynchronize(b->stream));
-                if (bad) {
-                    tune_log("batch", b->dtype, b->n, 0, 0, c, INFINITY, "parity-failed");
-                    continue;
-                }
-            }
-            if (ci == 0 && cands.size() > 1) continue;
-            std::vector<float> t;
-            for (int r = 0; r < repeats; ++r) {
-                HIPCHK(hipEventRecord(b->ev0, b->stream));
-                b->run(n_sweeps, 0.8, out);
-                HIPCHK(hipEventRecord(b->ev1, b->stream));
-                HIPCHK(hipEventSynchronize(b->ev1));
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
-                t.push_back(ms);
-            }
-            const double med = t[median_index_sort(t)];
-            tune_log("batch", b->dtype, b->n, 0, 0, c, med, "ok");
-            if (med < win_ms) {
-                win_ms = med;
-                win = c;
-            }
-        }
+            b->cfg.use_graph = 1;
+            b->reserve(ev.n_sweeps);
+        };
+        ev.ops.restore = [this] { restore(); };
+        ev.ops.run = [this](int n) { b->run(n, 0.8, static_cast<double*>(b->gosa.p)); };
+        ev.ops.result = [this] { return std::make_pair((const void*)b->slab, b->slab_bytes); };
+    }
+    void restore()
+    {
+        HIPCHK(hipMemcpyAsync(b->slab, save.p, b->slab_bytes, hipMemcpyDeviceToDevice, b->stream));
+        b->parity = par0;
+    }
+    int finish(const hj_config& win, double win_ms, hj_config* best, double* best_ms)
+    {
         restore();
         HIPCHK(hipStreamSynchronize(b->stream));
         b->graphs.clear();
@@ -1532,13 +1622,118 @@ int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, do
             b->tiled = false;
             return set_err(HJ_ERR_TUNE, "no candidate configuration passed");
         }
-        win.use_graph = keep.use_graph;
         b->cfg = win;
-        cache_put("batch", b->dtype, batch_key(b->L), win, win_ms);
-        if (best) *best = win;
+        b->cfg.use_graph = keep.use_graph;
+        cache_put("batch", b->dtype, batch_key(b->L), b->cfg, win_ms);
+        if (best) *best = b->cfg;
         if (best_ms) *best_ms = win_ms;
         return HJ_OK;
+    }
+};
+
+int batch_tunable(hj_batch b, int n_sweeps, int repeats)
+{
+    if (int rc = check_batch(b)) return rc;
+    if (n_sweeps < 1 || repeats < 1) return set_err(HJ_ERR_ARG, "n_sweeps and repeats must be >= 1");
+    if (!b->all_uploaded()) return set_err(HJ_ERR_STATE, "not every input field of every instance is uploaded");
+    return HJ_OK;
+}
+
+std::vector<hj_config> batch_candidates(int dtype)
+{
+    std::vector<hj_config> out;
+    const int vmax = dtype == HJ_F64 ? 2 : 4;
+    for (int bj : {1, 2, 4, 8})
+        for (int v = 1; v <= vmax; v *= 2)
+            for (int ich : {2, 4, 8, 16, 32})
+                for (int nt : {0, 1})
+                    for (int per : {0, 1}) {
+                        hj_config c = batch_default(dtype);
+                        c.bj = bj; c.vec = v; c.ichunk = ich; c.nontemporal = nt; c.persistent = per;
+                        if (config_supported(dtype, c)) out.push_back(c);
+                    }
+    return out;
+}
+
+}  // namespace
+
+int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, double* best_ms)
+{
+    if (int rc = batch_tunable(b, n_sweeps, repeats)) return rc;
+    return guarded([&]() -> int {
+        BatchTuning tu(b, n_sweeps, repeats);
+        hj_config refc = batch_default(b->dtype);
+        refc.nontemporal = 0;
+        tu.ev.eval(refc);
+        hj_config win = tu.keep;
+        double win_ms = INFINITY;
+        for (const hj_config& c : batch_candidates(b->dtype)) {
+            const double ms = tu.ev.eval(c);
+            if (ms < win_ms) {
+                win_ms = ms;
+                win = c;
+            }
+        }
+        return tu.finish(win, win_ms, best, best_ms);
     });
+}
+
+int hj_batch_autotune_ga(hj_batch b, int population, int generations, unsigned long long seed, double pc,
+                         double pm, int n_sweeps, int repeats, hj_config* best, double* best_ms,
+                         int* evaluations)
+{
+    if (int rc = batch_tunable(b, n_sweeps, repeats)) return rc;
+    if (population < 1 || generations < 1 || !(pc >= 0.0 && pc <= 1.0) || !(pm >= 0.0 && pm <= 1.0))
+        return set_err(HJ_ERR_ARG, "need population, generations >= 1 and 0 <= pc, pm <= 1");
+    return guarded([&]() -> int {
+        BatchTuning tu(b, n_sweeps, repeats);
+        hj_config refc = batch_default(b->dtype);
+        refc.nontemporal = 0;
+        tu.ev.eval(refc);
+        auto time_of = [&](uint32_t g) -> double {
+            hj_config c;
+            if (!decode_gene(g, b->dtype, 0, 0, 0, true, c)) return hjga::kFailTime;
+            const double ms = tu.ev.eval(c);
+            return std::isfinite(ms) ? ms * 1e-3 : hjga::kFailTime;
+        };
+        const hjga::Result r = hjga::run(kGeneBits, population, generations, seed, pc, pm, time_of);
+        hj_config win = tu.keep;
+        double win_ms = INFINITY;
+        if (r.best_time < hjga::kFailTime && decode_gene(r.best_gene, b->dtype, 0, 0, 0, true, win))
+            win_ms = r.best_time * 1e3;
+        if (evaluations) *evaluations = r.evaluations;
+        return tu.finish(win, win_ms, best, best_ms);
+    });
+}
+
+int hj_ga_run(int gene_bits, int population, int generations, unsigned long long seed, double pc, double pm,
+              const double* time_of_gene, unsigned* best_gene, double* best_time, unsigned* history,
+              int* evaluations)
+{
+    if (gene_bits < 1 || gene_bits > 20 || population < 1 || generations < 1 || !time_of_gene ||
+        !(pc >= 0.0 && pc <= 1.0) || !(pm >= 0.0 && pm <= 1.0))
+        return set_err(HJ_ERR_ARG, "bad genetic search arguments");
+    return guarded([&]() -> int {
+        const hjga::Result r = hjga::run(gene_bits, population, generations, seed, pc, pm,
+                                         [&](uint32_t g) { return time_of_gene[g]; });
+        if (best_gene) *best_gene = r.best_gene;
+        if (best_time) *best_time = r.best_time;
+        if (evaluations) *evaluations = r.evaluations;
+        if (history)
+            for (size_t q = 0; q < r.history.size(); ++q) history[q] = r.history[q];
+        return HJ_OK;
+    });
+}
+
+int hj_gene_config(int dtype, int nx, int ny, int nz, int batch, unsigned gene, hj_config* out)
+{
+    if (!out) return set_err(HJ_ERR_ARG, "out is NULL");
+    if (int rc = check_dtype(dtype)) return rc;
+    hj_config c;
+    if (!decode_gene(gene, dtype, nx, ny, nz, batch != 0, c))
+        return set_err(HJ_ERR_ARG, "gene 0x%x names no configuration", gene);
+    *out = c;
+    return HJ_OK;
 }
 
 int hj_batch_destroy(hj_batch b)

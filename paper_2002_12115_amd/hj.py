@@ -100,6 +100,10 @@ def load() -> ctypes.CDLL:
         "hj_batch_destroy": [H],
         "hj_copy_probe": [vp, vp, u64, vp, dp],
         "hj_stream_probe": [H, i32, i32, i32, dp],
+        "hj_autotune_ga": [H, i32, i32, u64, dbl, dbl, i32, i32, cp, dp, ip],
+        "hj_batch_autotune_ga": [H, i32, i32, u64, dbl, dbl, i32, i32, cp, dp, ip],
+        "hj_gene_config": [i32, i32, i32, i32, i32, ctypes.c_uint, cp],
+        "hj_ga_run": [i32, i32, i32, u64, dbl, dbl, vp, ctypes.POINTER(ctypes.c_uint), dp, vp, ip],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -268,6 +272,17 @@ class Solver:
               "hj_autotune")
         return c, float(ms.value)
 
+    def autotune_ga(self, population: int = 10, generations: int = 10, seed: int = 2002, pc: float = 0.9,
+                    pm: float = 0.05, n_sweeps: int = 3, repeats: int = 3) -> Tuple[Config, float, int]:
+        """The paper's genetic search over the configuration (returns config, ms, evaluations)."""
+        c = Config()
+        ms = ctypes.c_double()
+        ev = ctypes.c_int()
+        check(self.lib.hj_autotune_ga(self._h, int(population), int(generations), int(seed), float(pc), float(pm),
+                                      int(n_sweeps), int(repeats), ctypes.byref(c), ctypes.byref(ms),
+                                      ctypes.byref(ev)), "hj_autotune_ga")
+        return c, float(ms.value), int(ev.value)
+
     def close(self) -> None:
         if self._h:
             check(self.lib.hj_destroy(self._h), "hj_destroy")
@@ -369,6 +384,16 @@ class Batch:
         check(self.lib.hj_batch_autotune(self._h, int(n_sweeps), int(repeats), ctypes.byref(c),
                                          ctypes.byref(ms)), "hj_batch_autotune")
         return c, float(ms.value)
+
+    def autotune_ga(self, population: int = 10, generations: int = 10, seed: int = 2002, pc: float = 0.9,
+                    pm: float = 0.05, n_sweeps: int = 3, repeats: int = 3) -> Tuple[Config, float, int]:
+        c = Config()
+        ms = ctypes.c_double()
+        ev = ctypes.c_int()
+        check(self.lib.hj_batch_autotune_ga(self._h, int(population), int(generations), int(seed), float(pc),
+                                            float(pm), int(n_sweeps), int(repeats), ctypes.byref(c),
+                                            ctypes.byref(ms), ctypes.byref(ev)), "hj_batch_autotune_ga")
+        return c, float(ms.value), int(ev.value)
 
     def close(self) -> None:
         if self._h:

@@ -101,3 +101,18 @@ def test_batch_errors():
                                       xcd_remap=0, persistent=0)
         with pytest.raises(ValueError):
             b.upload(1, "p", np.zeros((4, 4, 4)))
+
+
+def test_batch_genetic_search_keeps_parity():
+    shapes, seeds = small_batch(3, 5)
+    arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
+    with hj.Batch("f64", shapes) as b:
+        for t, a in enumerate(arrays):
+            b.upload_all(t, a)
+        say("batch genetic search")
+        best, ms, evals = b.autotune_ga(population=8, generations=6, seed=1, n_sweeps=2, repeats=1)
+        assert ms > 0 and best.kernel == 1 and evals >= 1
+        b.sweep(4, 0.8)
+        for t, a in enumerate(arrays):
+            pref, _, _ = oracle.sweep(a, 4, 0.8)
+            assert np.array_equal(b.download(t), pref)

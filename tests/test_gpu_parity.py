@@ -216,3 +216,25 @@ def test_autotune_restores_state_and_keeps_parity():
             assert np.array_equal(p, pref), best
         else:
             assert field_err(p, pref) <= F32_FIELD_RTOL
+
+
+def test_genetic_search_restores_state_and_keeps_parity():
+    shape = (40, 36, 140)
+    f = inputs.fields(7, shape)
+    for dtype in ("f64", "f32"):
+        with hj.Solver(dtype, shape) as s:
+            s.upload_all(f)
+            s.sweep(2, 0.8)
+            before = s.download("p")
+            say("genetic search", dtype)
+            best, ms, evals = s.autotune_ga(population=10, generations=10, seed=2002, n_sweeps=2, repeats=1)
+            assert ms > 0 and 1 <= evals <= 100
+            assert np.array_equal(s.download("p"), before)
+            assert s.config.as_dict() == dict(best.as_dict(), use_graph=1)
+            s.sweep(3, 0.8)
+            p = s.download("p")
+        pref, _ = oracle_run(shape, 5, seed=7)
+        if dtype == "f64":
+            assert np.array_equal(p, pref), best
+        else:
+            assert field_err(p, pref) <= F32_FIELD_RTOL
