@@ -202,8 +202,13 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
     wall = time.perf_counter() - t0
     updates = n_int * w.iters * steps
     glups = updates / wall / 1e9
-    launches = w.iters * steps
-    bytes_per_launch = 14 * esize(w.dtype) * n_int
+    # Algorithmic bytes: 13 reads + 1 write per lattice update (14 x element
+    # size). A two-iteration launch updates every interior cell twice; the
+    # odd remainder of a solve runs one single-iteration launch, whose time is
+    # folded in pro rata (one iteration = half a two-iteration launch).
+    tsteps = 2 if cfg.get("tsteps") == 2 else 1
+    launches = w.iters * steps / tsteps
+    bytes_per_launch = 14 * esize(w.dtype) * n_int * tsteps
     avg_launch_ms = kernel_ms / launches
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     traffic = load_traffic(w.name, cfg)
@@ -217,7 +222,7 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
         sv = 2 if w.dtype == "f64" else 4
         st_ms = min(s.stream_probe(sv, ich, 10) for ich in (2, 4, 8))
         ceilings = {"copy_gbps": 2 * nb / copy_ms / 1e6,
-                    "stream13r1w_gbps": bytes_per_launch / st_ms / 1e6}
+                    "stream13r1w_gbps": 14 * esize(w.dtype) * n_int / st_ms / 1e6}
         ceilings["frac_of_stream13r1w"] = achieved / ceilings["stream13r1w_gbps"]
     res = {
         "glups": glups, "ms_per_step": wall * 1e3 / steps, "wall_s": wall, "ceilings": ceilings,
@@ -253,21 +258,26 @@ def tuner_comparison(w, hj, inputs, arrays):
     return out
 
 
-def run_transfer_contrast(w, args, hj, inputs, arrays, n_iter: int):
-    """The same solve with a host round trip of p every iteration."""
-    s = hj.Solver(w.dtype, w.shape)
-    s.upload_all(arrays)
-    host = np.empty(w.shape, dtype=np.float64 if w.dtype == "f64" else np.float32)
-    s.sweep(1, w.omega)
-    t0 = time.perf_counter()
-    for _ in range(n_iter):
-        s.sweep(1, w.omega)
-        host[...] = s.download("p")
-        s.upload("p", host)
-    dt = time.perf_counter() - t0
-    s.close()
-    return {"glups": interior(w.shape) * n_iter / dt / 1e9, "iters": n_iter,
-            "ms_per_iter": dt * 1e3 / n_iter}
+def transfer_ablation(w, hj, arrays):
+    """The same solve under the transfer placements of paper_2002_12115_amd.transfer."""
+    from paper_2002_12115_amd import transfer
+    out = {}
+    ref = None
+    for policy, n in (("resident", w.iters), ("p_every_k", w.iters), ("p_every_iter", 20),
+                      ("all_every_iter", 10)):
+        s = hj.Solver(w.dtype, w.shape)
+        r = transfer.run(s, arrays, policy, n, w.omega, k=10)
+        s.close()
+        if policy == "resident":
+            ref = r
+        same = None
+        if n == ref["iters"]:
+            same = bool(np.array_equal(r["field"], ref["field"]))
+        out[policy] = {"glups": interior(w.shape) * n / r["wall_s"] / 1e9, "iters": n, "k": r["k"],
+                       "ms_per_iter": r["wall_s"] * 1e3 / n,
+                       "pcie_gbps": (r["h2d_bytes"] + r["d2h_bytes"]) / r["wall_s"] / 1e9,
+                       "field_equals_resident": same}
+    return out
 
 
 def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune: bool):
@@ -382,7 +392,12 @@ def main():
     hj.load()
     w = inputs.WORKLOADS[args.workload]
     if w.batch:
-        raise SystemExit("use a single-solve workload for the main line; batch64 is reported under extra")
+        if not args.profile:
+            raise SystemExit("the main line is a single solve; batch64 is reported under extra "
+                             "(or run it alone with --profile)")
+        r = run_batch(args, hj, inputs, "f32", w.iters, False, args.retune)
+        print(json.dumps({"workload": w.name, "batch64_f32_batched": r}), flush=True)
+        return
     if args.profile:
         args.no_cpu_baseline = True
         args.no_extra = True
@@ -413,7 +428,9 @@ def main():
                    "omega": w.omega, "seed": w.seed, "kernel_config": res["config"]},
         "roofline": {"bound": "hbm", "achieved": res["hbm_gbps_alg"], "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": res["frac_peak"], "traffic": res["traffic"],
-                     "kernel": "march_kernel" if res["config"]["kernel"] == 1 else "direct_kernel",
+                     "kernel": ("direct_kernel" if res["config"]["kernel"] == 0 else
+                                "fused_kernel" if res["config"].get("tsteps") == 2 else "march_kernel"),
+                     "lattice_updates_per_launch": interior(w.shape) * (2 if res["config"].get("tsteps") == 2 else 1),
                      "bytes_per_launch": res["bytes_per_launch"],
                      "avg_launch_ms": res["avg_launch_ms"], "measured_ceilings": res["ceilings"]},
         "hbm_gbps_alg": res["hbm_gbps_alg"],
@@ -428,8 +445,8 @@ def main():
         extra = {}
         log("tuner comparison...")
         extra["tuner_exhaustive_vs_genetic"] = tuner_comparison(w, hj, inputs, arrays)
-        log("transfer contrast...")
-        extra["roundtrip_p_every_iteration"] = run_transfer_contrast(w, args, hj, inputs, arrays, 20)
+        log("transfer placement...")
+        extra["transfer_placement"] = transfer_ablation(w, hj, arrays)
         log("batch64 FP32 batched...")
         extra["batch64_f32_batched"] = run_batch(args, hj, inputs, "f32", 100, False, args.retune)
         log("batch64 FP64 batched...")

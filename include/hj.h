@@ -71,7 +71,16 @@ enum hj_field {
  * stores. use_graph: replay the sweep loop as a captured HIP graph.
  * xcd_remap: renumber workgroups so neighbouring tiles share an XCD's L2.
  * persistent (batches only): launch as many workgroups as stay resident and
- * let each loop over tiles, instead of one workgroup per tile. */
+ * let each loop over tiles, instead of one workgroup per tile.
+ * tsteps: Jacobi iterations per pass over memory (single solves). 1, or 2:
+ * the march kernel computes the first iteration of a tile and its one-cell
+ * halo into LDS and the second from it, so each coefficient is read once
+ * per two iterations (needs kernel HJ_KERNEL_MARCH, vec 1, bj 2, 4, 8 or 14;
+ * an odd remainder runs one single-iteration launch). 0 means 1. The
+ * results are bitwise those of tsteps 1.
+ * reread (tsteps 2 only): 0 holds each cell's coefficients in registers
+ * between its two iterations, 1 reads them again for the second (an L2 hit
+ * when nontemporal is 0), which frees registers for more resident waves. */
 typedef struct hj_config {
     int kernel;
     int bj;
@@ -81,6 +90,8 @@ typedef struct hj_config {
     int use_graph;
     int xcd_remap;
     int persistent;
+    int tsteps;
+    int reread;
 } hj_config;
 
 enum { HJ_KERNEL_DIRECT = 0, HJ_KERNEL_MARCH = 1 };
@@ -143,10 +154,10 @@ int hj_set_config(hj_solver h, const hj_config* cfg);
 int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double* best_ms);
 
 /* The paper's genetic search (sections 4 and 5.1.2) as the search strategy
- * of the autotuner, instead of trying every candidate. A gene is 10 bits
- * (bit 0 kernel, bits 1-2 bj = 1,2,4,8, bits 3-4 vec = 1,2,4, bits 5-7 one of
- * eight i-chunk lengths, bit 8 non-temporal, bit 9 XCD renumbering; see
- * hj_gene_config). population and generations individuals are measured as
+ * of the autotuner, instead of trying every candidate. A gene is 11 bits and
+ * every value names a configuration (hj_gene_config): bit 0 kernel, bits 1-2
+ * bj, bits 3-4 vec, bits 5-7 one of eight i-chunk lengths, bit 8
+ * non-temporal, bit 9 XCD renumbering, bit 10 two iterations per pass. population and generations individuals are measured as
  * by hj_autotune (same parity gate) with fitness (time)^(-1/2); a failed
  * measurement or a gene that names no configuration counts as 1000 s.
  * Roulette selection with elitism, one-point crossover with probability pc,
@@ -159,8 +170,12 @@ int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long l
                    double pm, int n_sweeps, int repeats, hj_config* best, double* best_ms,
                    int* evaluations);
 
-/* The configuration a gene names for this problem (batch != 0: for a batch,
- * where bit 9 selects the persistent grid). HJ_ERR_ARG if it names none. */
+/* The configuration a gene names for this problem. bits 1-2: bj 1, 2, 4, 8
+ * (the direct kernel reads 1 as 2, two-iteration passes read it as 14);
+ * bits 3-4: vec 1, 2, 1, 2 (FP64) or 1, 2, 4, 4 (FP32) for the one-iteration
+ * march kernel, and bit 3 is reread for two-iteration passes; bits 5-7 pick the i-chunk giving about 512 << n workgroups
+ * (64 << n for two-iteration passes; 2^n for batches). batch != 0: for a
+ * batch, always the march kernel, bit 9 the persistent grid, bit 10 unused. */
 int hj_gene_config(int dtype, int nx, int ny, int nz, int batch, unsigned gene, hj_config* out);
 
 /* The same genetic search with the time of every gene given by a table

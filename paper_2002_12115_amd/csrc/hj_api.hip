@@ -140,10 +140,23 @@ hj_config default_config(int dtype)
     c.use_graph = 1;
     c.xcd_remap = 0;
     c.persistent = 0;
+    c.tsteps = 1;
+    c.reread = 0;
     return c;
 }
 
 bool same_config(const hj_config& a, const hj_config& b) { return memcmp(&a, &b, sizeof a) == 0; }
+
+// The i-chunk that gives a grid about `target` workgroups under config c.
+int ichunk_for(const hj_config& c, int nx, int ny, int nz, long long target)
+{
+    hj_config u = c;
+    u.ichunk = 1;
+    const TileCounts one = tile_counts(u, nx, ny, nz);
+    const long long base = std::max<long long>(1, (long long)one.kt_n * one.jt_n);
+    const long long nchunks = std::max<long long>(1, (target + base - 1) / base);
+    return (int)std::max<long long>(1, (nx - 2 + nchunks - 1) / nchunks);
+}
 
 // Reference configuration of the autotuner's parity gate: the plainest kernel.
 hj_config reference_config(int dtype)
@@ -293,8 +306,9 @@ void tune_log(const char* what, int dtype, int nx, int ny, int nz, const hj_conf
     if (!path || !*path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s,%s,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%.6f,%s\n", what, dtype == HJ_F64 ? "f64" : "f32", nx,
-            ny, nz, c.kernel, c.bj, c.vec, c.ichunk, c.nontemporal, c.xcd_remap, c.persistent, ms, verdict);
+    fprintf(f, "%s,%s,%d,%d,%d,%d,%d,%d,%d,%d,%d,%d,%.6f,%s,%d,%d\n", what, dtype == HJ_F64 ? "f64" : "f32", nx,
+            ny, nz, c.kernel, c.bj, c.vec, c.ichunk, c.nontemporal, c.xcd_remap, c.persistent, ms, verdict, c.tsteps,
+            c.reread);
     fclose(f);
 }
 
@@ -309,7 +323,7 @@ int median_index_sort(std::vector<float>& t)
 // With HJ_TUNE_CACHE=<path>, every successful autotune records its winner as
 // one text line, and a new handle whose (kind, GPU architecture, dtype,
 // shape key) matches a line starts from that configuration:
-//   <kind> <arch> <f64|f32> <key> <kernel> <bj> <vec> <ichunk> <nt> <remap> <persistent> <ms>
+//   <kind> <arch> <f64|f32> <key> <kernel> <bj> <vec> <ichunk> <nt> <remap> <persistent> <ms> <tsteps> <reread>
 std::mutex g_cache_mu;
 
 const char* cache_path()
@@ -364,9 +378,12 @@ bool cache_get(const char* kind, int dtype, const std::string& key, hj_config& c
         char k[32], a[64], d[8], kk[128];
         hj_config x = default_config(dtype);
         double ms = 0;
-        if (sscanf(line, "%31s %63s %7s %127s %d %d %d %d %d %d %d %lf", k, a, d, kk, &x.kernel, &x.bj, &x.vec,
-                   &x.ichunk, &x.nontemporal, &x.xcd_remap, &x.persistent, &ms) != 12)
-            continue;
+        const int got = sscanf(line, "%31s %63s %7s %127s %d %d %d %d %d %d %d %lf %d %d", k, a, d, kk, &x.kernel,
+                               &x.bj, &x.vec, &x.ichunk, &x.nontemporal, &x.xcd_remap, &x.persistent, &ms,
+                               &x.tsteps, &x.reread);
+        if (got < 12) continue;
+        if (got < 13) x.tsteps = 1;
+        if (got < 14) x.reread = 0;
         if (strcmp(k, kind) || arch != a || strcmp(d, dtype == HJ_F64 ? "f64" : "f32") || key != kk) continue;
         c = x;
         found = true;  // the last matching line wins
@@ -397,8 +414,8 @@ void cache_put(const char* kind, int dtype, const std::string& key, const hj_con
     FILE* f = fopen(path, "w");
     if (!f) return;
     for (const std::string& l : keep) fputs(l.c_str(), f);
-    fprintf(f, "%s %s %s %s %d %d %d %d %d %d %d %.6f\n", kind, arch.c_str(), d, key.c_str(), c.kernel, c.bj,
-            c.vec, c.ichunk, c.nontemporal, c.xcd_remap, c.persistent, ms);
+    fprintf(f, "%s %s %s %s %d %d %d %d %d %d %d %.6f %d %d\n", kind, arch.c_str(), d, key.c_str(), c.kernel,
+            c.bj, c.vec, c.ichunk, c.nontemporal, c.xcd_remap, c.persistent, ms, c.tsteps, c.reread);
     fclose(f);
 }
 
@@ -471,39 +488,49 @@ struct Evaluator {
 
 // ---- the genetic search's gene ------------------------------------------------
 //
-// 10 bits: bit 0 kernel (0 direct, 1 march), bits 1-2 bj = 1,2,4,8, bits 3-4
-// vec = 1,2,4 (3 is not a configuration), bits 5-7 one of 8 i-chunk lengths,
-// bit 8 non-temporal streams, bit 9 XCD renumbering (single solve) or
-// persistent grid (batch). A gene that names no configuration scores as a
-// failed measurement.
-constexpr int kGeneBits = 10;
+// 11 bits, every value naming a configuration (codes that do not apply to a
+// mode are ignored, unusable ones fold onto usable ones):
+//   bit 0      kernel: 0 direct, 1 march (batches: always march)
+//   bits 1-2   bj: 1, 2, 4, 8 (direct: 1 reads as 2; two-iteration: 1 reads as 14)
+//   bits 3-4   vec (march, one iteration): FP64 1, 2, 1, 2; FP32 1, 2, 4, 4;
+//              bit 3 is reread for two-iteration passes
+//   bits 5-7   one of 8 i-chunk lengths (march kernels)
+//   bit 8      non-temporal streams
+//   bit 9      XCD renumbering (single solve) / persistent grid (batch)
+//   bit 10     two iterations per pass (single solve, march kernel)
+constexpr int kGeneBits = 11;
 
 // The 8 i-chunk lengths a gene can name for one grid: the chunk that gives
-// about 512, 1024, ..., 65536 workgroups.
+// about 512, 1024, ..., 65536 workgroups (64 .. 8192 for two-iteration passes,
+// whose chunks recompute their halo planes).
 int gene_ichunk(int sel, const hj_config& c, int nx, int ny, int nz)
 {
-    const long long kt = (nz - 2 + 64 * c.vec - 1) / (64 * c.vec);
-    const long long jt = (ny - 2 + c.bj - 1) / c.bj;
-    const long long target = 512LL << sel;
-    const long long nchunks = std::max<long long>(1, (target + kt * jt - 1) / (kt * jt));
-    return (int)std::max<long long>(1, (nx - 2 + nchunks - 1) / nchunks);
+    const long long target = fused_of(c) ? (64LL << sel) : (512LL << sel);
+    return ichunk_for(c, nx, ny, nz, target);
 }
 
 bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_config& c)
 {
+    static const int kBj[4] = {1, 2, 4, 8};
+    static const int kVec64[4] = {1, 2, 1, 2}, kVec32[4] = {1, 2, 4, 4};
     c = default_config(dtype);
-    c.kernel = (g & 1) ? HJ_KERNEL_MARCH : HJ_KERNEL_DIRECT;
-    c.bj = 1 << ((g >> 1) & 3);
-    const int vi = (g >> 3) & 3;
-    if (vi == 3) return false;
-    c.vec = 1 << vi;
-    const int sel = (g >> 5) & 7;
+    c.kernel = (batch || (g & 1)) ? HJ_KERNEL_MARCH : HJ_KERNEL_DIRECT;
+    c.tsteps = (!batch && c.kernel == HJ_KERNEL_MARCH && ((g >> 10) & 1)) ? 2 : 1;
+    const int bi = (g >> 1) & 3, vi = (g >> 3) & 3, sel = (g >> 5) & 7;
+    c.bj = kBj[bi];
+    c.vec = dtype == HJ_F64 ? kVec64[vi] : kVec32[vi];
     c.nontemporal = (g >> 8) & 1;
     c.xcd_remap = batch ? 0 : (int)((g >> 9) & 1);
     c.persistent = batch ? (int)((g >> 9) & 1) : 0;
     if (c.kernel == HJ_KERNEL_DIRECT) {
-        if (batch || c.vec != 1 || sel != 0) return false;  // one spelling per direct configuration
+        if (c.bj == 1) c.bj = 2;
+        c.vec = 1;
         c.ichunk = 1;
+    } else if (c.tsteps == 2) {
+        if (c.bj == 1) c.bj = 14;
+        c.vec = 1;
+        c.reread = vi & 1;
+        c.ichunk = gene_ichunk(sel, c, nx, ny, nz);
     } else {
         c.ichunk = batch ? (1 << sel) : gene_ichunk(sel, c, nx, ny, nz);
     }
@@ -548,36 +575,80 @@ struct hj_solver_s {
         return g;
     }
 
-    long long tiles() const { return tile_counts(cfg, L.nx, L.ny, L.nz).tiles(); }
-
-    hipError_t launch_one(int par, double omega, bool write, double* part_out, hipStream_t st) const
+    // The single-iteration configuration: cfg itself, or, for two-iteration
+    // passes, the one that runs an odd remainder and the residual.
+    hj_config single_cfg() const
     {
-        if (dtype == HJ_F64) return launch_sweep<double>(cfg, grid<double>(par), omega, write, part_out, st);
-        return launch_sweep<float>(cfg, grid<float>(par), (float)omega, write, part_out, st);
+        if (!fused_of(cfg)) return cfg;
+        hj_config c = default_config(dtype);
+        c.ichunk = ichunk_for(c, L.nx, L.ny, L.nz, 4096);
+        c.nontemporal = cfg.nontemporal;
+        c.use_graph = cfg.use_graph;
+        return c;
+    }
+    long long tiles_of(const hj_config& c) const { return tile_counts(c, L.nx, L.ny, L.nz).tiles(); }
+    // Partials per iteration slot (room for either kernel's tiles).
+    long long stride() const { return std::max(tiles_of(cfg), tiles_of(single_cfg())); }
+    long long tiles() const { return tiles_of(cfg); }
+    // Iterations per block of partials; pairs of a two-iteration pass never straddle two blocks.
+    int chunk_of(int n_iter) const
+    {
+        int ch = chunk_iters(std::max(n_iter, 1), stride());
+        if (fused_of(cfg)) ch = std::max(2, ch & ~1);
+        return ch;
+    }
+    int launches(int n_iter) const { return fused_of(cfg) ? n_iter / 2 + (n_iter & 1) : n_iter; }
+
+    hipError_t launch_one(const hj_config& c, int par, double omega, bool write, double* part_out,
+                          hipStream_t st) const
+    {
+        if (dtype == HJ_F64) return launch_sweep<double>(c, grid<double>(par), omega, write, part_out, st);
+        return launch_sweep<float>(c, grid<float>(par), (float)omega, write, part_out, st);
+    }
+    hipError_t launch_two(int par, double omega, double* p1, double* p2, hipStream_t st) const
+    {
+        if (dtype == HJ_F64) return launch_fused<double>(cfg, grid<double>(par), omega, p1, p2, st);
+        return launch_fused<float>(cfg, grid<float>(par), (float)omega, p1, p2, st);
     }
 
-    // Enqueue n_iter sweeps starting from parity `par`, gosa history to out.
-    void enqueue(int n_iter, double omega, int par, double* out, hipStream_t st) const
+    // Enqueue n_iter iterations starting from parity `par`, gosa history to
+    // out. Returns the parity after them (one flip per launch).
+    int enqueue(int n_iter, double omega, int par, double* out, hipStream_t st) const
     {
-        const long long nt = tiles();
-        const int ch = chunk_iters(n_iter, nt);
+        const bool two = fused_of(cfg);
+        const hj_config one = single_cfg();
+        const long long sd = stride();
+        const int ch = chunk_of(n_iter);
         double* pt = static_cast<double*>(part.p);
-        int it0 = 0;
-        for (int it = 0; it < n_iter; ++it) {
-            const int slot = it - it0;
-            HIPCHK(launch_one(par, omega, true, pt + (long long)slot * nt, st));
-            par ^= 1;
-            if (slot + 1 == ch || it == n_iter - 1) {
-                HIPCHK(launch_finalize(pt, nt, (int)nt, nullptr, 1, slot + 1, out + it0, st));
-                it0 = it + 1;
+        for (int it0 = 0; it0 < n_iter;) {
+            const int n_here = std::min(ch, n_iter - it0);
+            int slot = 0;
+            if (two) {
+                for (; slot + 1 < n_here; slot += 2) {
+                    HIPCHK(launch_two(par, omega, pt + slot * sd, pt + (slot + 1) * sd, st));
+                    par ^= 1;
+                }
+                if (slot > 0)
+                    HIPCHK(launch_finalize(pt, sd, (int)tiles_of(cfg), nullptr, 1, slot, out + it0, st));
             }
+            if (slot < n_here) {
+                const int first = slot;
+                const hj_config& c = two ? one : cfg;
+                for (; slot < n_here; ++slot) {
+                    HIPCHK(launch_one(c, par, omega, true, pt + slot * sd, st));
+                    par ^= 1;
+                }
+                HIPCHK(launch_finalize(pt + first * sd, sd, (int)tiles_of(c), nullptr, 1, slot - first,
+                                       out + it0 + first, st));
+            }
+            it0 += n_here;
         }
+        return par;
     }
 
     void reserve(int n_iter)
     {
-        const long long nt = tiles();
-        const size_t need_part = (size_t)chunk_iters(std::max(n_iter, 1), nt) * (size_t)nt * 8;
+        const size_t need_part = (size_t)chunk_of(n_iter) * (size_t)stride() * 8;
         const size_t need_gosa = (size_t)std::max(n_iter, 1) * 8;
         if (need_part > part.bytes || need_gosa > gosa.bytes) {
             graphs.clear();  // graphs hold the old addresses
@@ -597,10 +668,10 @@ struct hj_solver_s {
                 graphs.add(GraphEntry{n_iter, bits_of(omega), parity, cfg, out, ex});
             }
             HIPCHK(hipGraphLaunch(ex, stream));
+            parity ^= (launches(n_iter) & 1);
         } else {
-            enqueue(n_iter, omega, parity, out, stream);
+            parity = enqueue(n_iter, omega, parity, out, stream);
         }
-        parity ^= (n_iter & 1);
     }
 };
 
@@ -819,6 +890,26 @@ std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch)
                         if (config_supported(dtype, x)) out.push_back(x);
                     }
         }
+    if (!batch) {
+        // two iterations per pass: long chunks (the halo planes of a chunk are recomputed)
+        for (int bj : {4, 8, 14})
+            for (int target : {256, 512, 1024, 2048})
+                for (int nt : {0, 1})
+                    for (int rr : {0, 1}) {
+                        hj_config x = base;
+                        x.kernel = HJ_KERNEL_MARCH;
+                        x.bj = bj;
+                        x.vec = 1;
+                        x.tsteps = 2;
+                        x.reread = rr;
+                        x.nontemporal = nt;
+                        x.xcd_remap = 0;
+                        x.ichunk = ichunk_for(x, nx, ny, nz, target);
+                        bool dup = false;
+                        for (const hj_config& y : out) dup = dup || same_config(x, y);
+                        if (!dup && config_supported(dtype, x)) out.push_back(x);
+                    }
+    }
     return out;
 }
 
@@ -990,8 +1081,9 @@ int hj_residual(hj_solver h, double* gosa)
         h->reserve(1);
         double* pt = static_cast<double*>(h->part.p);
         double* out = static_cast<double*>(h->gosa.p);
-        const long long nt = h->tiles();
-        HIPCHK(h->launch_one(h->parity, 0.0, false, pt, h->stream));
+        const hj_config one = h->single_cfg();
+        const long long nt = h->tiles_of(one);
+        HIPCHK(h->launch_one(one, h->parity, 0.0, false, pt, h->stream));
         HIPCHK(launch_finalize(pt, nt, (int)nt, nullptr, 1, 1, out, h->stream));
         h->host_gosa.ensure(8);
         HIPCHK(hipMemcpyAsync(h->host_gosa.p, out, 8, hipMemcpyDeviceToHost, h->stream));
@@ -1017,6 +1109,8 @@ int hj_set_config(hj_solver h, const hj_config* cfg)
         h->graphs.clear();
         h->cfg = *cfg;
         h->cfg.persistent = 0;
+        if (h->cfg.tsteps == 0) h->cfg.tsteps = 1;
+        if (h->cfg.tsteps == 1) h->cfg.reread = 0;
         return HJ_OK;
     });
 }
@@ -1123,11 +1217,16 @@ int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long l
         SolverTuning tu(h, n_sweeps, repeats);
         tu.ev.eval(reference_config(h->dtype));
         const Layout& L = h->L;
+        std::vector<std::pair<hj_config, double>> seen;  // one measurement per configuration
         auto time_of = [&](uint32_t g) -> double {
             hj_config c;
             if (!decode_gene(g, h->dtype, L.nx, L.ny, L.nz, false, c)) return hjga::kFailTime;
+            for (auto& e : seen)
+                if (same_config(e.first, c)) return e.second;
             const double ms = tu.ev.eval(c);
-            return std::isfinite(ms) ? ms * 1e-3 : hjga::kFailTime;
+            const double t = std::isfinite(ms) ? ms * 1e-3 : hjga::kFailTime;
+            seen.emplace_back(c, t);
+            return t;
         };
         const hjga::Result r = hjga::run(kGeneBits, population, generations, seed, pc, pm, time_of);
         hj_config win = tu.keep;
@@ -1566,10 +1665,13 @@ int hj_batch_set_config(hj_batch b, const hj_config* cfg)
     if (int rc = check_batch(b)) return rc;
     if (int rc = validate_config(b->dtype, cfg)) return rc;
     if (cfg->kernel != HJ_KERNEL_MARCH) return set_err(HJ_ERR_ARG, "batches run the march kernel only");
+    if (cfg->tsteps == 2) return set_err(HJ_ERR_ARG, "batches run one iteration per pass");
     return guarded([&]() -> int {
         b->graphs.clear();
         b->cfg = *cfg;
         b->cfg.xcd_remap = 0;
+        b->cfg.tsteps = 1;
+        b->cfg.reread = 0;
         return HJ_OK;
     });
 }
@@ -1690,11 +1792,16 @@ int hj_batch_autotune_ga(hj_batch b, int population, int generations, unsigned l
         hj_config refc = batch_default(b->dtype);
         refc.nontemporal = 0;
         tu.ev.eval(refc);
+        std::vector<std::pair<hj_config, double>> seen;
         auto time_of = [&](uint32_t g) -> double {
             hj_config c;
             if (!decode_gene(g, b->dtype, 0, 0, 0, true, c)) return hjga::kFailTime;
+            for (auto& e : seen)
+                if (same_config(e.first, c)) return e.second;
             const double ms = tu.ev.eval(c);
-            return std::isfinite(ms) ? ms * 1e-3 : hjga::kFailTime;
+            const double t = std::isfinite(ms) ? ms * 1e-3 : hjga::kFailTime;
+            seen.emplace_back(c, t);
+            return t;
         };
         const hjga::Result r = hjga::run(kGeneBits, population, generations, seed, pc, pm, time_of);
         hj_config win = tu.keep;

@@ -115,6 +115,11 @@ int batch_occ_bj(const hj_config& c)
 bool config_supported(int dtype, const hj_config& c)
 {
     if (dtype != HJ_F64 && dtype != HJ_F32) return false;
+    if (c.tsteps < 0 || c.tsteps > 2 || c.reread < 0 || c.reread > 1) return false;
+    if (c.xcd_remap < 0 || c.xcd_remap > 1) return false;
+    if (c.tsteps == 2)
+        return c.kernel == HJ_KERNEL_MARCH && c.vec == 1 && c.ichunk >= 1 && c.persistent == 0 &&
+               (c.bj == 2 || c.bj == 4 || c.bj == 8 || c.bj == 14);
     if (!bj_ok(c.bj)) return false;
     if (c.kernel == HJ_KERNEL_DIRECT) return c.bj >= 2;
     if (c.kernel != HJ_KERNEL_MARCH) return false;
@@ -126,6 +131,7 @@ template <typename T>
 hipError_t launch_sweep(const hj_config& c, const Grid<T>& g, T omega, bool write, double* part,
                         hipStream_t st)
 {
+    if (fused_of(c)) return hipErrorInvalidValue;
     if (c.kernel == HJ_KERNEL_DIRECT) {
         switch (c.bj) {
         case 2: return HJ_DISPATCH_NT(direct_go, T, 2, 1, c, g, omega, part, st);
@@ -168,6 +174,54 @@ int batch_occupancy(const hj_config& c)
     default: return 0;
     }
 }
+
+namespace {
+
+template <typename T, int BJ, bool NT, bool KEEP>
+hipError_t fused_go(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
+                    hipStream_t st)
+{
+    const TileCounts t = tile_counts(c, g.nx, g.ny, g.nz);
+    const long long nb = t.tiles();
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((fused_kernel<T, BJ, NT, KEEP>), dim3((unsigned)nb), dim3(kWave * (BJ + 2)), 0, st, g, omega,
+                       c.ichunk, t.kt_n, t.jt_n, c.xcd_remap, part1, part2);
+    return hipGetLastError();
+}
+
+template <typename T, int BJ>
+hipError_t fused_bj(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
+                    hipStream_t st)
+{
+    if (c.reread) {
+        return c.nontemporal ? fused_go<T, BJ, true, false>(c, g, omega, part1, part2, st)
+                             : fused_go<T, BJ, false, false>(c, g, omega, part1, part2, st);
+    }
+    return c.nontemporal ? fused_go<T, BJ, true, true>(c, g, omega, part1, part2, st)
+                         : fused_go<T, BJ, false, true>(c, g, omega, part1, part2, st);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
+                        hipStream_t st)
+{
+    if (!fused_of(c) || c.kernel != HJ_KERNEL_MARCH || c.vec != 1 || c.ichunk < 1) return hipErrorInvalidValue;
+    switch (c.bj) {
+    case 2: return fused_bj<T, 2>(c, g, omega, part1, part2, st);
+    case 4: return fused_bj<T, 4>(c, g, omega, part1, part2, st);
+    case 8: return fused_bj<T, 8>(c, g, omega, part1, part2, st);
+    case 14: return fused_bj<T, 14>(c, g, omega, part1, part2, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_fused<double>(const hj_config&, const Grid<double>&, double, double*, double*,
+                                         hipStream_t);
+template hipError_t launch_fused<float>(const hj_config&, const Grid<float>&, float, double*, double*,
+                                        hipStream_t);
 
 template hipError_t launch_sweep<double>(const hj_config&, const Grid<double>&, double, bool,
                                          double*, hipStream_t);

@@ -14,9 +14,20 @@ struct TileCounts {
 
 inline int vec_of(const hj_config& c) { return c.kernel == HJ_KERNEL_DIRECT ? 1 : c.vec; }
 
+inline bool fused_of(const hj_config& c) { return c.tsteps == 2; }
+
+// Own k cells per tile of the two-iteration kernel (a 64-lane row minus its halo).
+constexpr int kFusedTK = kWave - 2;
+
 inline TileCounts tile_counts(const hj_config& c, int nx, int ny, int nz)
 {
     TileCounts t;
+    if (fused_of(c)) {
+        t.kt_n = (nz - 2 + kFusedTK - 1) / kFusedTK;
+        t.jt_n = (ny - 2 + c.bj - 1) / c.bj;
+        t.ic_n = chunks(nx, c.ichunk);
+        return t;
+    }
     const int tk = kWave * vec_of(c);
     t.kt_n = (nz - 2 + tk - 1) / tk;
     t.jt_n = (ny - 2 + c.bj - 1) / c.bj;
@@ -31,6 +42,12 @@ bool config_supported(int dtype, const hj_config& c);
 // one FP64 partial per tile (tile_counts(...).tiles() of them).
 template <typename T>
 hipError_t launch_sweep(const hj_config& c, const Grid<T>& g, T omega, bool write, double* part,
+                        hipStream_t st);
+
+// Two iterations over a single grid (tsteps 2): g.src -> g.dst, with the
+// first iteration's per-tile gosa partials to part1 and the second's to part2.
+template <typename T>
+hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                         hipStream_t st);
 
 // One iteration over every instance of a batch.

@@ -382,6 +382,207 @@ __global__ __launch_bounds__(kWave * BJ) void direct_kernel(Grid<T> g, T omega, 
     if (threadIdx.x == 0) part[L] = acc;
 }
 
+// ---- fused kernel: two Jacobi iterations per pass over HBM -------------------
+//
+// A workgroup of BJ+2 waves owns a tile of BJ rows x 62 cells and marches
+// along i. Wave r, lane l sits on the extended cell (j0-1+r, k0-1+l), so the
+// waves together cover the tile plus a one-cell halo in j and k. At step i
+// every thread computes the first iteration at its extended cell of plane i
+// (p1, from p0 planes i-1..i+1 staged in an LDS ring with a two-cell halo)
+// into a second LDS ring. After a barrier the tile's own cells compute the
+// second iteration at plane i-1 from p1 planes i-2..i, and only p2 goes back
+// to memory. Each thread keeps the 12 coefficients of its own cell from the
+// first iteration for the second, so the coefficient arrays are read once
+// per two iterations; the halo cells cost their coefficient reads again
+// (overlapped tiling). Cells on the domain shell carry p0 unchanged into p1.
+// Each interior cell's first-iteration ss is summed by the workgroup that
+// owns it, so both iterations' gosa are exact partitions.
+template <typename T, int BJ>
+struct alignas(16) FusedLds {
+    static constexpr int XW = kWave;      // extended row: k0-1 .. k0+62
+    static constexpr int TK = XW - 2;     // own cells per row
+    static constexpr int R1 = BJ + 2;     // rows of p1 (j0-1 .. j0+BJ)
+    static constexpr int R0 = BJ + 4;     // rows of p0 (j0-2 .. j0+BJ+1)
+    static constexpr int W0 = XW + 2;     // cols of p0 (k0-2 .. k0+63)
+    T p0[4][R0][W0];
+    T p1[4][R1][XW];
+    double red[BJ + 2];
+};
+
+template <typename T>
+struct P0Regs {
+    T own, lo, hi, col;
+};
+
+// Fetch p0 plane ii for the tile: own extended cell, row j0-2 (wave 0),
+// row j0+BJ+1 (last wave) and columns k0-2 / k0+63 (threads < 2*(BJ+4)).
+template <typename T, int BJ>
+__device__ __forceinline__ void fused_fetch(const Grid<T>& g, int ii, int j0, int k0, P0Regs<T>& r)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const T* base = g.src + (long long)ii * g.S;
+    const int k = k0 - 1 + lane, j = j0 - 1 + w;
+    if (j <= g.ny - 1 && k <= g.nz - 1) r.own = base[(long long)j * g.P + k];
+    if (w == 0 && j0 - 2 >= 0 && k <= g.nz - 1) r.lo = base[(long long)(j0 - 2) * g.P + k];
+    if (w == BJ + 1 && j0 + BJ + 1 <= g.ny - 1 && k <= g.nz - 1)
+        r.hi = base[(long long)(j0 + BJ + 1) * g.P + k];
+    const int t = threadIdx.x;
+    if (t < 2 * (BJ + 4)) {
+        const int jj = j0 - 2 + (t >> 1);
+        const int kk = (t & 1) ? k0 + kWave - 1 : k0 - 2;
+        if (jj >= 0 && jj <= g.ny - 1 && kk >= 0 && kk <= g.nz - 1) r.col = base[(long long)jj * g.P + kk];
+    }
+}
+
+template <typename T, int BJ>
+__device__ __forceinline__ void fused_put(const Grid<T>& g, T (*pl)[FusedLds<T, BJ>::W0], int j0, int k0,
+                                          const P0Regs<T>& r)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int k = k0 - 1 + lane, j = j0 - 1 + w;
+    if (j <= g.ny - 1 && k <= g.nz - 1) pl[w + 1][lane + 1] = r.own;
+    if (w == 0 && j0 - 2 >= 0 && k <= g.nz - 1) pl[0][lane + 1] = r.lo;
+    if (w == BJ + 1 && j0 + BJ + 1 <= g.ny - 1 && k <= g.nz - 1) pl[BJ + 3][lane + 1] = r.hi;
+    const int t = threadIdx.x;
+    if (t < 2 * (BJ + 4)) {
+        const int jj = j0 - 2 + (t >> 1);
+        const int kk = (t & 1) ? k0 + kWave - 1 : k0 - 2;
+        if (jj >= 0 && jj <= g.ny - 1 && kk >= 0 && kk <= g.nz - 1) pl[t >> 1][(t & 1) ? kWave + 1 : 0] = r.col;
+    }
+}
+
+// KEEP: hold the own cell's coefficients in registers for the second
+// iteration; otherwise re-read them (they were read one step earlier, so the
+// read is served by L2 when the first read was not non-temporal).
+template <typename T, int BJ, bool NT, bool KEEP>
+__device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, int jt, int ib, int ie,
+                                           FusedLds<T, BJ>& sm, double& acc1, double& acc2)
+{
+    constexpr int TK = FusedLds<T, BJ>::TK;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int k0 = 1 + kt * TK, j0 = 1 + jt * BJ;
+    const int k = k0 - 1 + lane, j = j0 - 1 + w;               // this thread's extended cell
+    const bool in_dom = (j <= g.ny - 1) && (k <= g.nz - 1);
+    const bool jk_int = in_dom && j >= 1 && j <= g.ny - 2 && k >= 1 && k <= g.nz - 2;
+    const bool own = (w >= 1 && w <= BJ && lane >= 1 && lane <= TK);
+    const bool out = own && jk_int;                             // an output cell of this tile
+    const int rho = w + 1, c = lane + 1;                        // position in the p0 tile
+    const long long rowoff = (long long)j * g.P + k;
+
+    // p0 planes ib-2 .. ib (clipped at the shell)
+    const int i_lo = ib - 1, i_hi = ie;                          // first-iteration planes
+    P0Regs<T> rr;
+    for (int ii = i_lo - 1; ii <= i_lo + 1; ++ii) {
+        if (ii < 0) continue;
+        fused_fetch<T, BJ>(g, ii, j0, k0, rr);
+        fused_put<T, BJ>(g, sm.p0[ii & 3], j0, k0, rr);
+    }
+    __syncthreads();
+
+    T keep[KEEP ? NCOEF : 1];          // own cell's coefficients of the previous plane
+#pragma unroll
+    for (int q = 0; q < (KEEP ? NCOEF : 1); ++q) keep[q] = T(0);
+    for (int i = i_lo; i <= i_hi; ++i) {
+        const bool more = (i + 2 <= i_hi + 1) && (i + 2 <= g.nx - 1);
+        if (more) fused_fetch<T, BJ>(g, i + 2, j0, k0, rr);
+
+        // ---- first iteration at plane i, extended cell (j, k)
+        T cur[NCOEF];
+        const bool interior = jk_int && i >= 1 && i <= g.nx - 2;
+        if (in_dom) {
+            auto* Pm = sm.p0[(i - 1) & 3];
+            auto* Pc = sm.p0[i & 3];
+            auto* Pp = sm.p0[(i + 1) & 3];
+            T p1v;
+            if (interior) {
+                const long long o = (long long)i * g.S + rowoff;
+#pragma unroll
+                for (int q = 0; q < NCOEF; ++q) cur[q] = sload<T, NT>(g.coef[q] + o);
+                const T pc = Pc[rho][c];
+                const T ss = cell_ss<T>(cur[CA0], cur[CA1], cur[CA2], cur[CA3], cur[CB0], cur[CB1], cur[CB2],
+                                        cur[CC0], cur[CC1], cur[CC2], cur[CBND], cur[CWRK1],
+                                        Pp[rho][c], Pc[rho + 1][c], Pc[rho][c + 1],
+                                        bracket(Pp[rho + 1][c], Pp[rho - 1][c], Pm[rho + 1][c], Pm[rho - 1][c]),
+                                        bracket(Pc[rho + 1][c + 1], Pc[rho - 1][c + 1], Pc[rho + 1][c - 1],
+                                                Pc[rho - 1][c - 1]),
+                                        bracket(Pp[rho][c + 1], Pm[rho][c + 1], Pp[rho][c - 1], Pm[rho][c - 1]),
+                                        Pm[rho][c], Pc[rho - 1][c], Pc[rho][c - 1], pc);
+                p1v = pc + omega * ss;
+                if (out && i >= ib && i < ie) {
+                    const double d = (double)ss;
+                    acc1 += d * d;
+                }
+            } else {
+                p1v = Pc[rho][c];                              // the shell is never updated
+            }
+            sm.p1[i & 3][w][lane] = p1v;
+        }
+        if (more) fused_put<T, BJ>(g, sm.p0[(i + 2) & 3], j0, k0, rr);
+        __syncthreads();
+
+        // ---- second iteration at plane i-1, own cells
+        const int i2 = i - 1;
+        if (out && i2 >= ib && i2 < ie) {
+            auto* Qm = sm.p1[(i2 - 1) & 3];
+            auto* Qc = sm.p1[i2 & 3];
+            auto* Qp = sm.p1[(i2 + 1) & 3];
+            const T qc = Qc[w][lane];
+            T kc[NCOEF];
+            if constexpr (KEEP) {
+#pragma unroll
+                for (int q = 0; q < NCOEF; ++q) kc[q] = keep[q];
+            } else {
+                const long long o2 = (long long)i2 * g.S + rowoff;
+#pragma unroll
+                for (int q = 0; q < NCOEF; ++q) kc[q] = g.coef[q][o2];
+            }
+            const T ss = cell_ss<T>(kc[CA0], kc[CA1], kc[CA2], kc[CA3], kc[CB0], kc[CB1], kc[CB2],
+                                    kc[CC0], kc[CC1], kc[CC2], kc[CBND], kc[CWRK1],
+                                    Qp[w][lane], Qc[w + 1][lane], Qc[w][lane + 1],
+                                    bracket(Qp[w + 1][lane], Qp[w - 1][lane], Qm[w + 1][lane], Qm[w - 1][lane]),
+                                    bracket(Qc[w + 1][lane + 1], Qc[w - 1][lane + 1], Qc[w + 1][lane - 1],
+                                            Qc[w - 1][lane - 1]),
+                                    bracket(Qp[w][lane + 1], Qm[w][lane + 1], Qp[w][lane - 1], Qm[w][lane - 1]),
+                                    Qm[w][lane], Qc[w - 1][lane], Qc[w][lane - 1], qc);
+            const T outv = qc + omega * ss;
+            T* dst = g.dst + (long long)i2 * g.S + rowoff;
+            if constexpr (NT) __builtin_nontemporal_store(outv, dst);
+            else *dst = outv;
+            const double d = (double)ss;
+            acc2 += d * d;
+        }
+        if constexpr (KEEP) {
+            if (interior) {
+#pragma unroll
+                for (int q = 0; q < NCOEF; ++q) keep[q] = cur[q];
+            }
+        }
+    }
+}
+
+template <typename T, int BJ, bool NT, bool KEEP>
+__global__ __launch_bounds__(kWave * (BJ + 2)) void fused_kernel(Grid<T> g, T omega, int ichunk, int kt_n,
+                                                                  int jt_n, int remap,
+                                                                  double* __restrict__ part1,
+                                                                  double* __restrict__ part2)
+{
+    __shared__ FusedLds<T, BJ> sm;
+    const int nb = gridDim.x;
+    const int L = remap_xcd(blockIdx.x, nb, remap);
+    const int kt = L % kt_n;
+    const int jt = (L / kt_n) % jt_n;
+    const int ic = L / (kt_n * jt_n);
+    const int ib = 1 + ic * ichunk;
+    int ie = ib + ichunk;
+    if (ie > g.nx - 1) ie = g.nx - 1;
+    double acc1 = 0.0, acc2 = 0.0;
+    fused_tile<T, BJ, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
+    acc1 = block_sum<BJ + 2>(acc1, sm.red);
+    if (threadIdx.x == 0) part1[L] = acc1;
+    acc2 = block_sum<BJ + 2>(acc2, sm.red);
+    if (threadIdx.x == 0) part2[L] = acc2;
+}
+
 // ---- batch: many grids, one launch over a flattened tile list ---------------
 
 

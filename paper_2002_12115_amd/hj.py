@@ -34,7 +34,8 @@ class HJError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int), ("bj", ctypes.c_int), ("vec", ctypes.c_int),
                 ("ichunk", ctypes.c_int), ("nontemporal", ctypes.c_int), ("use_graph", ctypes.c_int),
-                ("xcd_remap", ctypes.c_int), ("persistent", ctypes.c_int)]
+                ("xcd_remap", ctypes.c_int), ("persistent", ctypes.c_int), ("tsteps", ctypes.c_int),
+                ("reread", ctypes.c_int)]
 
     def as_dict(self) -> Dict[str, int]:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}

@@ -1,0 +1,70 @@
+"""Where the CPU-GPU transfers of a solve are placed.
+
+The paper's offload method moves variables between CPU and GPU at the
+outermost loop it can (section 3.2). It sends variables that are not needed
+back and forth once, before all GPU work, and returns them after it; data
+already on the GPU is marked present (section 3.3). This module runs the same
+Jacobi solve under different placements, so the cost the rule avoids can be
+measured on MI355X. Every placement computes the same iterations with the
+same kernels; only the transfers around them differ, so the final field is
+bitwise the same.
+
+Placements:
+  resident          upload once, all iterations on the device, download once
+  p_every_k         the field goes to the host and back every k iterations
+  p_every_iter      ... every iteration
+  all_every_iter    all 13 inputs are uploaded before every iteration and the
+                    field is downloaded after it (per-loop offload with no
+                    data region)
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, Mapping
+
+import numpy as np
+
+from .inputs import INPUTS
+
+POLICIES = ("resident", "p_every_k", "p_every_iter", "all_every_iter")
+
+
+def run(solver, arrays: Mapping[str, np.ndarray], policy: str, n_iter: int, omega: float,
+        k: int = 10) -> Dict[str, object]:
+    """Upload `arrays`, run n_iter iterations under `policy`, return timings,
+    bytes moved, the final field and the gosa history."""
+    if policy not in POLICIES:
+        raise ValueError("unknown policy %r" % (policy,))
+    esz = np.dtype(solver.np_dtype).itemsize
+    cells = int(np.prod(solver.shape))
+    field_bytes = cells * esz
+    solver.upload_all(arrays)
+    host = np.array(solver.download("p"))           # the host's copy of the field
+    h2d = d2h = 0
+    hist = []
+    t0 = time.perf_counter()
+    if policy == "resident":
+        solver.sweep(n_iter, omega)
+        hist.extend(solver.gosa_history)
+    else:
+        step = k if policy == "p_every_k" else 1
+        done = 0
+        while done < n_iter:
+            n = min(step, n_iter - done)
+            if policy == "all_every_iter":
+                for name in INPUTS:
+                    solver.upload(name, host if name == "p" else arrays[name])
+                h2d += len(INPUTS) * field_bytes
+            solver.sweep(n, omega)
+            hist.extend(solver.gosa_history)
+            host = solver.download("p")
+            d2h += field_bytes
+            if policy != "all_every_iter":
+                solver.upload("p", host)
+                h2d += field_bytes
+            done += n
+    wall = time.perf_counter() - t0
+    final = solver.download("p")
+    return {"policy": policy, "iters": n_iter, "k": k if policy == "p_every_k" else None,
+            "wall_s": wall, "h2d_bytes": h2d, "d2h_bytes": d2h, "field": final,
+            "gosa_history": np.asarray(hist)}

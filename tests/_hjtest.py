@@ -50,7 +50,7 @@ def oracle_run(shape, n_iter, omega=0.8, seed=2002, bnd_mode=0, nthreads=8, arra
 
 def cfg(**kw):
     base = dict(kernel=hj.KERNEL_MARCH, bj=4, vec=1, ichunk=8, nontemporal=1, use_graph=1,
-                xcd_remap=1, persistent=0)
+                xcd_remap=1, persistent=0, tsteps=1, reread=0)
     base.update(kw)
     return hj.Config.make(**base)
 
@@ -64,6 +64,16 @@ def f64_configs():
         for v in (1, 2):
             for ich, nt, rm in ((1, 1, 0), (3, 0, 1), (16, 1, 1), (1000, 0, 0)):
                 out.append(cfg(bj=bj, vec=v, ichunk=ich, nontemporal=nt, xcd_remap=rm))
+    out.extend(fused_configs())
+    return out
+
+
+def fused_configs():
+    """Two iterations per pass (tsteps 2)."""
+    out = []
+    for bj in (2, 4, 8, 14):
+        for ich, nt, rm, rr in ((1, 1, 0, 0), (2, 0, 1, 1), (5, 1, 0, 1), (1000, 0, 1, 0)):
+            out.append(cfg(bj=bj, vec=1, ichunk=ich, nontemporal=nt, xcd_remap=rm, tsteps=2, reread=rr))
     return out
 
 
@@ -73,10 +83,11 @@ def f32_configs():
         for v in (1, 2, 4):
             for ich, nt, rm in ((2, 1, 1), (7, 0, 0)):
                 out.append(cfg(bj=bj, vec=v, ichunk=ich, nontemporal=nt, xcd_remap=rm))
+    out.extend(fused_configs())
     return out
 
 
 def cfg_id(c):
     d = c.as_dict()
-    k = "direct" if d["kernel"] == 0 else "march"
+    k = "direct" if d["kernel"] == 0 else ("fused%d" % d["reread"] if d["tsteps"] == 2 else "march")
     return "%s-bj%d-v%d-ic%d-nt%d-rm%d" % (k, d["bj"], d["vec"], d["ichunk"], d["nontemporal"], d["xcd_remap"])

@@ -158,25 +158,32 @@ def test_gene_decoding(lib):
                                    ctypes.c_uint, ctypes.POINTER(hj.Config)]
     lib.hj_gene_config.restype = ctypes.c_int
     c = hj.Config()
+
+    def dec(dtype, gene, batch=0, shape=(130, 130, 258)):
+        assert lib.hj_gene_config(dtype, *shape, batch, gene, ctypes.byref(c)) == 0
+        return c.as_dict()
     # march, bj 4, vec 2, chunk choice 0, non-temporal, no remap
-    g = 1 | (2 << 1) | (1 << 3) | (0 << 5) | (1 << 8)
-    assert lib.hj_gene_config(0, 130, 130, 258, 0, g, ctypes.byref(c)) == 0
-    d = c.as_dict()
-    assert (d["kernel"], d["bj"], d["vec"], d["nontemporal"], d["xcd_remap"]) == (1, 4, 2, 1, 0)
-    assert d["ichunk"] >= 1
-    # vec code 3 names nothing; vec 4 is FP32 only; direct with bj 1 is not a kernel
-    assert lib.hj_gene_config(0, 130, 130, 258, 0, 1 | (3 << 3), ctypes.byref(c)) == -1
-    assert lib.hj_gene_config(0, 130, 130, 258, 0, 1 | (2 << 3), ctypes.byref(c)) == -1
-    assert lib.hj_gene_config(1, 130, 130, 258, 0, 1 | (2 << 3), ctypes.byref(c)) == 0
-    assert lib.hj_gene_config(0, 130, 130, 258, 0, 0, ctypes.byref(c)) == -1
+    d = dec(0, 1 | (2 << 1) | (1 << 3) | (1 << 8))
+    assert (d["kernel"], d["bj"], d["vec"], d["nontemporal"], d["xcd_remap"], d["tsteps"]) == (1, 4, 2, 1, 0, 1)
+    # every gene names a configuration, for both dtypes, solves and batches
+    for dtype in (0, 1):
+        for batch in (0, 1):
+            for g in range(2 ** 11):
+                d = dec(dtype, g, batch)
+                if batch:
+                    assert d["kernel"] == 1 and d["tsteps"] == 1 and d["xcd_remap"] == 0
+    # folded codes: vec code 2 is 1 for FP64 and 4 for FP32; direct reads bj 1 as 2
+    assert dec(0, 1 | (2 << 3))["vec"] == 1 and dec(1, 1 | (2 << 3))["vec"] == 4
+    assert dec(0, 0)["bj"] == 2 and dec(0, 0)["kernel"] == 0
+    # two iterations per pass: march only, vec 1, bj code 0 reads as 14
+    d = dec(0, 1 | (1 << 10) | (3 << 3))
+    assert (d["tsteps"], d["vec"], d["bj"], d["reread"]) == (2, 1, 14, 1)
+    assert dec(0, 1 | (1 << 10) | (2 << 3))["reread"] == 0
+    assert dec(0, 1 << 10)["tsteps"] == 1              # bit 10 is ignored by the direct kernel
     # batch: bit 9 is the persistent grid, the chunk is 2^(bits 5-7)
-    g = 1 | (1 << 1) | (3 << 5) | (1 << 9)
-    assert lib.hj_gene_config(1, 0, 0, 0, 1, g, ctypes.byref(c)) == 0
-    d = c.as_dict()
+    d = dec(1, 1 | (1 << 1) | (3 << 5) | (1 << 9), batch=1, shape=(0, 0, 0))
     assert (d["persistent"], d["ichunk"], d["xcd_remap"]) == (1, 8, 0)
     # chunk choices shrink as the workgroup target grows
-    ch = []
-    for sel in range(8):
-        assert lib.hj_gene_config(0, 130, 130, 258, 0, 1 | (2 << 1) | (sel << 5), ctypes.byref(c)) == 0
-        ch.append(c.ichunk)
+    ch = [dec(0, 1 | (2 << 1) | (sel << 5))["ichunk"] for sel in range(8)]
     assert ch == sorted(ch, reverse=True) and ch[-1] == 1
+    assert lib.hj_gene_config(5, 130, 130, 258, 0, 0, ctypes.byref(c)) == -3

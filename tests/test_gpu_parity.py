@@ -238,3 +238,23 @@ def test_genetic_search_restores_state_and_keeps_parity():
             assert np.array_equal(p, pref), best
         else:
             assert field_err(p, pref) <= F32_FIELD_RTOL
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_transfer_placements_give_the_same_solve(dtype):
+    from paper_2002_12115_amd import transfer
+    shape = (34, 34, 66)
+    f = inputs.fields(2002, shape)
+    res = {}
+    for policy in transfer.POLICIES:
+        say("transfer", policy, dtype)
+        with hj.Solver(dtype, shape) as s:
+            res[policy] = transfer.run(s, f, policy, 12, 0.8, k=5)
+    ref = res["resident"]
+    for policy, r in res.items():
+        assert np.array_equal(r["field"], ref["field"]), policy
+        assert np.array_equal(r["gosa_history"], ref["gosa_history"]), policy
+    assert res["p_every_iter"]["d2h_bytes"] == 12 * f["p"].size * (8 if dtype == "f64" else 4)
+    if dtype == "f64":
+        pref, _ = oracle_run(shape, 12)
+        assert np.array_equal(ref["field"], pref)
