@@ -1,0 +1,89 @@
+"""Randomised GPU parity: shapes with dims 3..70 (odd sizes, k not a multiple
+of the tile), random bnd masks, iteration counts and kernel configurations,
+each compared with the oracle (FP64 bitwise, FP32 to 1e-5)."""
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings, strategies as st
+
+import oracle
+from paper_2002_12115_amd import hj, inputs
+from _hjtest import F32_FIELD_RTOL, F64_GOSA_RTOL, cfg, cfg_id, field_err, gosa_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@st.composite
+def configs(draw, dtype):
+    kind = draw(st.sampled_from(["direct", "march", "fused"]))
+    nt = draw(st.integers(0, 1))
+    rm = draw(st.integers(0, 1))
+    if kind == "direct":
+        return cfg(kernel=hj.KERNEL_DIRECT, bj=draw(st.sampled_from([2, 4, 8])), nontemporal=nt, xcd_remap=rm)
+    if kind == "march":
+        vecs = [1, 2] if dtype == "f64" else [1, 2, 4]
+        return cfg(bj=draw(st.sampled_from([1, 2, 4, 8])), vec=draw(st.sampled_from(vecs)),
+                   ichunk=draw(st.integers(1, 40)), nontemporal=nt, xcd_remap=rm)
+    return cfg(bj=draw(st.sampled_from([2, 4, 8, 14])), vec=1, ichunk=draw(st.integers(1, 40)), nontemporal=nt,
+               xcd_remap=rm, tsteps=2, reread=draw(st.integers(0, 1)))
+
+
+@settings(max_examples=60, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.data_too_large])
+@given(st.data())
+def test_random_shapes_and_configs(data):
+    dtype = data.draw(st.sampled_from(["f64", "f32"]))
+    shape = tuple(data.draw(st.integers(3, 70)) for _ in range(3))
+    n = data.draw(st.integers(1, 6))
+    bnd_mode = data.draw(st.integers(0, 1))
+    seed = data.draw(st.integers(0, 2 ** 32))
+    c = data.draw(configs(dtype))
+    say("fuzz", dtype, shape, n, bnd_mode, seed, cfg_id(c))
+    f = inputs.fields(seed, shape, bnd_mode=bnd_mode)
+    with hj.Solver(dtype, shape) as s:
+        s.config = c
+        s.upload_all(f)
+        s.sweep(n, 0.8)
+        p, hist = s.download("p"), s.gosa_history.copy()
+    pref, _, href = oracle.sweep(f, n, 0.8)
+    if dtype == "f64":
+        assert np.array_equal(p, pref)
+        assert gosa_err(hist, href) <= F64_GOSA_RTOL or np.all(href == 0)
+    else:
+        assert field_err(p, pref) <= F32_FIELD_RTOL
+
+
+def test_torch_side_stream_ordering():
+    """Work on a caller's (torch) stream stays ordered with the caller's own work."""
+    import torch
+    shape = (40, 30, 90)
+    f = inputs.fields(1, shape)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        say("side stream")
+        with hj.Solver("f64", shape, stream=side.cuda_stream) as s:
+            assert s.stream == side.cuda_stream
+            s.upload_all(f)
+            s.sweep_async(5, 0.8)                # enqueued only
+            marker = torch.ones(1, device="cuda")
+            marker.add_(1.0)                     # torch work queued after it on the same stream
+            s.sync()
+            side.synchronize()
+            assert marker.item() == 2.0
+            p = s.download("p")
+    pref, _, _ = oracle.sweep(f, 5, 0.8)
+    assert np.array_equal(p, pref)
+
+
+def test_sweep_async_device_history_into_torch_tensor():
+    import torch
+    shape = (20, 21, 70)
+    f = inputs.fields(7, shape)
+    hist = torch.zeros(6, dtype=torch.float64, device="cuda")
+    with hj.Solver("f64", shape) as s:
+        s.upload_all(f)
+        s.sweep_async(6, 0.8, hist.data_ptr())
+        s.sync()
+        p = s.download("p")
+    pref, _, href = oracle.sweep(f, 6, 0.8)
+    assert np.array_equal(p, pref)
+    assert gosa_err(hist.cpu().numpy(), href) <= F64_GOSA_RTOL
