@@ -246,14 +246,14 @@ def tuner_comparison(w, hj, inputs, arrays):
         os.environ["HJ_TUNE_CACHE"], saved = "", os.environ.get("HJ_TUNE_CACHE", "")
         t0 = time.perf_counter()
         if kind == "exhaustive":
-            c, ms = s.autotune(n_sweeps=5, repeats=3)
+            c, ms = s.autotune(n_sweeps=6, repeats=3)
             ev = None
         else:
-            c, ms, ev = s.autotune_ga(10, 10, w.seed, 0.9, 0.05, n_sweeps=5, repeats=3)
+            c, ms, ev = s.autotune_ga(10, 10, w.seed, 0.9, 0.05, n_sweeps=6, repeats=3)
         dt = time.perf_counter() - t0
         os.environ["HJ_TUNE_CACHE"] = saved
-        out[kind] = {"ms_per_sweep": ms / 5, "config": c.as_dict(), "evaluations": ev, "tune_s": dt,
-                     "hbm_gbps_alg": 14 * esize(w.dtype) * interior(w.shape) / (ms / 5) / 1e6}
+        out[kind] = {"ms_per_sweep": ms / 6, "config": c.as_dict(), "evaluations": ev, "tune_s": dt,
+                     "hbm_gbps_alg": 14 * esize(w.dtype) * interior(w.shape) / (ms / 6) / 1e6}
         s.close()
     return out
 
@@ -315,7 +315,7 @@ def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune
         for t, (sh, sd) in enumerate(zip(shapes, seeds)):
             b.upload_all(t, inputs.fields(sd, sh))
         if tune or not cache_has("batch", dtype, batch_key(shapes)):
-            c, ms = b.autotune(n_sweeps=5, repeats=3)
+            c, ms = b.autotune(n_sweeps=6, repeats=3)
             log("batch autotuned", dtype, c, ms)
         else:
             log("batch configuration from the tuning cache:", dtype, b.config)
@@ -364,7 +364,8 @@ def main():
                     help="autotune even when the tuning cache has this problem")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="also run the library's copy kernel over this many bytes (counter calibration)")
-    ap.add_argument("--tune-sweeps", type=int, default=5)
+    ap.add_argument("--tune-sweeps", type=int, default=6,
+                    help="sweeps per tuning measurement (even, so two-iteration passes have no remainder)")
     ap.add_argument("--check-iters", type=int, default=-1,
                     help="iterations compared with the oracle (default: all for small grids)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

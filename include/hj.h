@@ -62,8 +62,12 @@ enum hj_field {
 };
 
 /* Kernel choice. kernel: HJ_KERNEL_DIRECT (one thread per cell, neighbours
- * read through the caches) or HJ_KERNEL_MARCH (a (j,k) tile per workgroup
- * marching along i, p planes staged in an LDS ring). bj: rows of 64*vec
+ * read through the caches), HJ_KERNEL_MARCH (a (j,k) tile per workgroup
+ * marching along i, p planes staged in an LDS ring) or HJ_KERNEL_FLAT (a
+ * run of 64*bj consecutive interior cells of the flattened (j,k) plane per
+ * workgroup, marching along i, so no lane idles at the end of a k row; only
+ * for grids where the rows a run touches fit 10 KiB of LDS, e.g. nz up to
+ * about 600 in FP32 at bj 4; bj 2, 4 or 8, vec 1). bj: rows of 64*vec
  * cells per workgroup (1, 2, 4, 8). vec: consecutive k cells per lane (1, 2,
  * or 4 for HJ_F32; 1 or 2 for HJ_F64). ichunk: i planes per workgroup for the
  * march kernel (>= 1; splits the march so the grid fills the chip).
@@ -94,7 +98,7 @@ typedef struct hj_config {
     int reread;
 } hj_config;
 
-enum { HJ_KERNEL_DIRECT = 0, HJ_KERNEL_MARCH = 1 };
+enum { HJ_KERNEL_DIRECT = 0, HJ_KERNEL_MARCH = 1, HJ_KERNEL_FLAT = 2 };
 
 typedef struct hj_solver_s* hj_solver;
 typedef struct hj_batch_s* hj_batch;
@@ -149,7 +153,9 @@ int hj_set_config(hj_solver h, const hj_config* cfg);
  * there (one text line per GPU architecture, dtype and shape), and handles
  * created later for the same problem start from it. A candidate that fails
  * to launch or to match the reference is never chosen.
- * n_sweeps per timing (>= 1), repeats (>= 1): median of repeats is scored.
+ * n_sweeps per timing (>= 1; an even count times two-iteration passes
+ * without a one-iteration remainder), repeats (>= 1): the median of the
+ * repeats is scored.
  * best (nullable) receives the chosen configuration, best_ms its time. */
 int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double* best_ms);
 

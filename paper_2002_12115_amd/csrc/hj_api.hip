@@ -490,14 +490,16 @@ struct Evaluator {
 //
 // 11 bits, every value naming a configuration (codes that do not apply to a
 // mode are ignored, unusable ones fold onto usable ones):
-//   bit 0      kernel: 0 direct, 1 march (batches: always march)
+//   bit 0      kernel: 0 direct, 1 march; with bit 10: 0 flat, 1 march with
+//              two iterations per pass (batches: 0 flat, 1 march)
 //   bits 1-2   bj: 1, 2, 4, 8 (direct: 1 reads as 2; two-iteration: 1 reads as 14)
 //   bits 3-4   vec (march, one iteration): FP64 1, 2, 1, 2; FP32 1, 2, 4, 4;
 //              bit 3 is reread for two-iteration passes
 //   bits 5-7   one of 8 i-chunk lengths (march kernels)
 //   bit 8      non-temporal streams
 //   bit 9      XCD renumbering (single solve) / persistent grid (batch)
-//   bit 10     two iterations per pass (single solve, march kernel)
+//   bit 10     see bit 0 (single solves)
+// A flat kernel that does not fit the grid reads as the march kernel.
 constexpr int kGeneBits = 11;
 
 // The 8 i-chunk lengths a gene can name for one grid: the chunk that gives
@@ -514,15 +516,25 @@ bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_c
     static const int kBj[4] = {1, 2, 4, 8};
     static const int kVec64[4] = {1, 2, 1, 2}, kVec32[4] = {1, 2, 4, 4};
     c = default_config(dtype);
-    c.kernel = (batch || (g & 1)) ? HJ_KERNEL_MARCH : HJ_KERNEL_DIRECT;
-    c.tsteps = (!batch && c.kernel == HJ_KERNEL_MARCH && ((g >> 10) & 1)) ? 2 : 1;
+    const int b0 = g & 1, b10 = (g >> 10) & 1;
+    if (batch) c.kernel = b0 ? HJ_KERNEL_MARCH : HJ_KERNEL_FLAT;
+    else c.kernel = b0 ? HJ_KERNEL_MARCH : (b10 ? HJ_KERNEL_FLAT : HJ_KERNEL_DIRECT);
+    c.tsteps = (!batch && b0 && b10) ? 2 : 1;
     const int bi = (g >> 1) & 3, vi = (g >> 3) & 3, sel = (g >> 5) & 7;
     c.bj = kBj[bi];
     c.vec = dtype == HJ_F64 ? kVec64[vi] : kVec32[vi];
     c.nontemporal = (g >> 8) & 1;
     c.xcd_remap = batch ? 0 : (int)((g >> 9) & 1);
     c.persistent = batch ? (int)((g >> 9) & 1) : 0;
-    if (c.kernel == HJ_KERNEL_DIRECT) {
+    if (c.kernel == HJ_KERNEL_FLAT) {
+        if (c.bj == 1) c.bj = 2;
+        c.vec = 1;
+        c.ichunk = batch ? (1 << sel) : gene_ichunk(sel, c, nx, ny, nz);
+        if (!batch && !config_fits(dtype, c, nx, ny, nz)) {
+            c.kernel = HJ_KERNEL_MARCH;               // fold onto the march kernel
+            c.ichunk = gene_ichunk(sel, c, nx, ny, nz);
+        }
+    } else if (c.kernel == HJ_KERNEL_DIRECT) {
         if (c.bj == 1) c.bj = 2;
         c.vec = 1;
         c.ichunk = 1;
@@ -891,9 +903,24 @@ std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch)
                     }
         }
     if (!batch) {
+        // flat runs of consecutive (j,k) cells
+        for (int nw : {2, 4, 8})
+            for (int target : {1024, 2048, 4096, 8192})
+                for (int nt : {0, 1}) {
+                    hj_config x = base;
+                    x.kernel = HJ_KERNEL_FLAT;
+                    x.bj = nw;
+                    x.vec = 1;
+                    x.nontemporal = nt;
+                    x.xcd_remap = 0;
+                    x.ichunk = ichunk_for(x, nx, ny, nz, target);
+                    bool dup = false;
+                    for (const hj_config& y : out) dup = dup || same_config(x, y);
+                    if (!dup && config_fits(dtype, x, nx, ny, nz)) out.push_back(x);
+                }
         // two iterations per pass: long chunks (the halo planes of a chunk are recomputed)
         for (int bj : {4, 8, 14})
-            for (int target : {256, 512, 1024, 2048})
+            for (int target : {128, 256, 512, 1024, 2048, 4096})
                 for (int nt : {0, 1})
                     for (int rr : {0, 1}) {
                         hj_config x = base;
@@ -929,7 +956,8 @@ void apply_start_config(hj_solver h)
 {
     h->cfg.ichunk = default_ichunk(h->dtype, h->cfg, h->L.nx, h->L.ny, h->L.nz);
     hj_config c;
-    if (cache_get("solve", h->dtype, solve_key(h->L.nx, h->L.ny, h->L.nz), c) && config_supported(h->dtype, c)) {
+    if (cache_get("solve", h->dtype, solve_key(h->L.nx, h->L.ny, h->L.nz), c) &&
+        config_fits(h->dtype, c, h->L.nx, h->L.ny, h->L.nz)) {
         c.use_graph = 1;
         c.persistent = 0;
         h->cfg = c;
@@ -1105,6 +1133,9 @@ int hj_set_config(hj_solver h, const hj_config* cfg)
 {
     if (int rc = check_solver(h)) return rc;
     if (int rc = validate_config(h->dtype, cfg)) return rc;
+    if (!config_fits(h->dtype, *cfg, h->L.nx, h->L.ny, h->L.nz))
+        return set_err(HJ_ERR_ARG, "the flat kernel with bj %d does not fit a %dx%dx%d grid", cfg->bj, h->L.nx,
+                       h->L.ny, h->L.nz);
     return guarded([&]() -> int {
         h->graphs.clear();
         h->cfg = *cfg;
@@ -1141,6 +1172,8 @@ struct SolverTuning {
         ev.ops.e0 = h->ev0;
         ev.ops.e1 = h->ev1;
         ev.ops.set = [this](const hj_config& c) {
+            if (!config_fits(h->dtype, c, h->L.nx, h->L.ny, h->L.nz))
+                throw HipFail{hipErrorInvalidValue, "flat kernel does not fit", __LINE__};
             h->graphs.clear();
             h->cfg = c;
             h->cfg.use_graph = 0;
@@ -1398,6 +1431,9 @@ struct hj_batch_s {
     void build_tiles()
     {
         if (tiled && same_config(tiled_for, cfg)) return;
+        for (const Layout& l : L)  // every launch comes through here: never run a kernel that does not fit
+            if (!config_fits(dtype, cfg, l.nx, l.ny, l.nz))
+                throw HipFail{hipErrorInvalidValue, "configuration does not fit an instance", __LINE__};
         graphs.clear();
         if (dtype == HJ_F64) build_tiles_t<double>();
         else build_tiles_t<float>();
@@ -1471,6 +1507,13 @@ struct hj_batch_s {
 
 namespace {
 
+bool batch_fits(const hj_batch_s* b, const hj_config& c)
+{
+    for (const Layout& l : b->L)
+        if (!config_fits(b->dtype, c, l.nx, l.ny, l.nz)) return false;
+    return true;
+}
+
 int check_batch(hj_batch b)
 {
     if (!b || !reg_has(b) || b->magic != kBatchMagic)
@@ -1522,7 +1565,7 @@ int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* n
         {
             hj_config c;
             if (cache_get("batch", dtype, batch_key(b->L), c) && config_supported(dtype, c) &&
-                c.kernel == HJ_KERNEL_MARCH) {
+                c.kernel != HJ_KERNEL_DIRECT && c.tsteps != 2 && batch_fits(b, c)) {
                 c.use_graph = 1;
                 c.xcd_remap = 0;
                 b->cfg = c;
@@ -1664,8 +1707,9 @@ int hj_batch_set_config(hj_batch b, const hj_config* cfg)
 {
     if (int rc = check_batch(b)) return rc;
     if (int rc = validate_config(b->dtype, cfg)) return rc;
-    if (cfg->kernel != HJ_KERNEL_MARCH) return set_err(HJ_ERR_ARG, "batches run the march kernel only");
+    if (cfg->kernel == HJ_KERNEL_DIRECT) return set_err(HJ_ERR_ARG, "batches run the march or flat kernel");
     if (cfg->tsteps == 2) return set_err(HJ_ERR_ARG, "batches run one iteration per pass");
+    if (!batch_fits(b, *cfg)) return set_err(HJ_ERR_ARG, "the flat kernel does not fit every instance");
     return guarded([&]() -> int {
         b->graphs.clear();
         b->cfg = *cfg;
@@ -1701,6 +1745,7 @@ struct BatchTuning {
         ev.ops.e0 = b->ev0;
         ev.ops.e1 = b->ev1;
         ev.ops.set = [this](const hj_config& c) {
+            if (!batch_fits(b, c)) throw HipFail{hipErrorInvalidValue, "flat kernel does not fit", __LINE__};
             b->cfg = c;
             b->cfg.use_graph = 1;
             b->reserve(ev.n_sweeps);
@@ -1741,9 +1786,19 @@ int batch_tunable(hj_batch b, int n_sweeps, int repeats)
     return HJ_OK;
 }
 
-std::vector<hj_config> batch_candidates(int dtype)
+std::vector<hj_config> batch_candidates(const hj_batch_s* b)
 {
+    const int dtype = b->dtype;
     std::vector<hj_config> out;
+    for (int nw : {2, 4, 8})
+        for (int ich : {2, 4, 8, 16, 32})
+            for (int nt : {0, 1})
+                for (int per : {0, 1}) {
+                    hj_config c = batch_default(dtype);
+                    c.kernel = HJ_KERNEL_FLAT;
+                    c.bj = nw; c.vec = 1; c.ichunk = ich; c.nontemporal = nt; c.persistent = per;
+                    if (config_supported(dtype, c) && batch_fits(b, c)) out.push_back(c);
+                }
     const int vmax = dtype == HJ_F64 ? 2 : 4;
     for (int bj : {1, 2, 4, 8})
         for (int v = 1; v <= vmax; v *= 2)
@@ -1769,7 +1824,7 @@ int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, do
         tu.ev.eval(refc);
         hj_config win = tu.keep;
         double win_ms = INFINITY;
-        for (const hj_config& c : batch_candidates(b->dtype)) {
+        for (const hj_config& c : batch_candidates(b)) {
             const double ms = tu.ev.eval(c);
             if (ms < win_ms) {
                 win_ms = ms;

@@ -120,6 +120,7 @@ bool config_supported(int dtype, const hj_config& c)
     if (c.tsteps == 2)
         return c.kernel == HJ_KERNEL_MARCH && c.vec == 1 && c.ichunk >= 1 && c.persistent == 0 &&
                (c.bj == 2 || c.bj == 4 || c.bj == 8 || c.bj == 14);
+    if (c.kernel == HJ_KERNEL_FLAT) return (c.bj == 2 || c.bj == 4 || c.bj == 8) && c.vec == 1 && c.ichunk >= 1;
     if (!bj_ok(c.bj)) return false;
     if (c.kernel == HJ_KERNEL_DIRECT) return c.bj >= 2;
     if (c.kernel != HJ_KERNEL_MARCH) return false;
@@ -127,11 +128,65 @@ bool config_supported(int dtype, const hj_config& c)
     return dtype == HJ_F64 ? vec_ok<double>(c.vec) : vec_ok<float>(c.vec);
 }
 
+bool config_fits(int dtype, const hj_config& c, int nx, int ny, int nz)
+{
+    (void)nx;
+    if (!config_supported(dtype, c)) return false;
+    if (c.kernel == HJ_KERNEL_FLAT) return flat_fits(dtype == HJ_F64 ? 8 : 4, c.bj, ny, nz);
+    return true;
+}
+
+namespace {
+
+template <typename T, int NW, int V, bool NT, bool W>
+hipError_t flat_go(const hj_config& c, const Grid<T>& g, T omega, double* part, hipStream_t st)
+{
+    static_assert(kFlatPlaneBytes == kFlatPlaneBytesHost, "flat plane size");
+    if (!flat_fits((int)sizeof(T), NW, g.ny, g.nz)) return hipErrorInvalidValue;
+    const TileCounts t = tile_counts(c, g.nx, g.ny, g.nz);
+    const long long nb = t.tiles();
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((flat_kernel<T, NW, NT, W>), dim3((unsigned)nb), dim3(kWave * NW), 0, st, g, omega,
+                       c.ichunk, t.kt_n, c.xcd_remap, part);
+    return hipGetLastError();
+}
+
+template <typename T, int NW, int V, bool NT, bool W>
+hipError_t flat_batch_go(const Instance<T>* inst, const int* tile_inst, int ntiles, int grid, int parity,
+                         T omega, double* part, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((flat_batch_kernel<T, NW, NT, W>), dim3(grid), dim3(kWave * NW), 0, st, inst, tile_inst,
+                       ntiles, parity, omega, part);
+    return hipGetLastError();
+}
+
+template <typename T, int NW, bool NT>
+int flat_batch_occ()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, flat_batch_kernel<T, NW, NT, true>, kWave * NW, 0) !=
+        hipSuccess)
+        return 0;
+    return n;
+}
+
+}  // namespace
+
 template <typename T>
 hipError_t launch_sweep(const hj_config& c, const Grid<T>& g, T omega, bool write, double* part,
                         hipStream_t st)
 {
     if (fused_of(c)) return hipErrorInvalidValue;
+    if (c.kernel == HJ_KERNEL_FLAT) {
+        switch (c.bj) {
+        case 2: return HJ_DISPATCH_NT(flat_go, T, 2, 1, c, g, omega, part, st);
+        case 4: return HJ_DISPATCH_NT(flat_go, T, 4, 1, c, g, omega, part, st);
+        case 8: return HJ_DISPATCH_NT(flat_go, T, 8, 1, c, g, omega, part, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (c.kernel == HJ_KERNEL_DIRECT) {
         switch (c.bj) {
         case 2: return HJ_DISPATCH_NT(direct_go, T, 2, 1, c, g, omega, part, st);
@@ -154,6 +209,14 @@ hipError_t launch_batch(const hj_config& c, const Instance<T>* inst, const int* 
                         int ntiles, int grid, int parity, T omega, bool write, double* part,
                         hipStream_t st)
 {
+    if (c.kernel == HJ_KERNEL_FLAT) {
+        switch (c.bj) {
+        case 2: return HJ_DISPATCH_NT(flat_batch_go, T, 2, 1, inst, tile_inst, ntiles, grid, parity, omega, part, st);
+        case 4: return HJ_DISPATCH_NT(flat_batch_go, T, 4, 1, inst, tile_inst, ntiles, grid, parity, omega, part, st);
+        case 8: return HJ_DISPATCH_NT(flat_batch_go, T, 8, 1, inst, tile_inst, ntiles, grid, parity, omega, part, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (c.bj) {
     case 1: return batch_bj<T, 1>(c, inst, tile_inst, ntiles, grid, parity, omega, write, part, st);
     case 2: return batch_bj<T, 2>(c, inst, tile_inst, ntiles, grid, parity, omega, write, part, st);
@@ -166,6 +229,14 @@ hipError_t launch_batch(const hj_config& c, const Instance<T>* inst, const int* 
 template <typename T>
 int batch_occupancy(const hj_config& c)
 {
+    if (c.kernel == HJ_KERNEL_FLAT) {
+        switch (c.bj) {
+        case 2: return c.nontemporal ? flat_batch_occ<T, 2, true>() : flat_batch_occ<T, 2, false>();
+        case 4: return c.nontemporal ? flat_batch_occ<T, 4, true>() : flat_batch_occ<T, 4, false>();
+        case 8: return c.nontemporal ? flat_batch_occ<T, 8, true>() : flat_batch_occ<T, 8, false>();
+        default: return 0;
+        }
+    }
     switch (c.bj) {
     case 1: return batch_occ_bj<T, 1>(c);
     case 2: return batch_occ_bj<T, 2>(c);

@@ -19,12 +19,32 @@ inline bool fused_of(const hj_config& c) { return c.tsteps == 2; }
 // Own k cells per tile of the two-iteration kernel (a 64-lane row minus its halo).
 constexpr int kFusedTK = kWave - 2;
 
+// LDS bytes per staged plane of the flat kernel.
+constexpr int kFlatPlaneBytesHost = 10240;
+
+// Whether the flat kernel with 64*nw-cell runs fits a grid: the rows a run
+// touches, plus its halo rows, times nz, must fit one staged plane.
+inline bool flat_fits(int esz, int nw, int ny, int nz)
+{
+    const long long nzi = nz - 2, t = 64LL * nw;
+    long long rows = (t - 1 + nzi - 1) / nzi + 3;
+    if (rows > ny) rows = ny;
+    return rows * nz <= kFlatPlaneBytesHost / esz;
+}
+
 inline TileCounts tile_counts(const hj_config& c, int nx, int ny, int nz)
 {
     TileCounts t;
     if (fused_of(c)) {
         t.kt_n = (nz - 2 + kFusedTK - 1) / kFusedTK;
         t.jt_n = (ny - 2 + c.bj - 1) / c.bj;
+        t.ic_n = chunks(nx, c.ichunk);
+        return t;
+    }
+    if (c.kernel == HJ_KERNEL_FLAT) {
+        const long long cells = (long long)(ny - 2) * (nz - 2);
+        t.kt_n = (int)((cells + 64LL * c.bj - 1) / (64LL * c.bj));
+        t.jt_n = 1;
         t.ic_n = chunks(nx, c.ichunk);
         return t;
     }
@@ -37,6 +57,9 @@ inline TileCounts tile_counts(const hj_config& c, int nx, int ny, int nz)
 
 // True when (dtype, config) names an instantiated kernel.
 bool config_supported(int dtype, const hj_config& c);
+
+// True when the configuration is supported and can run this grid.
+bool config_fits(int dtype, const hj_config& c, int nx, int ny, int nz);
 
 // One sweep (write) or residual (no write) over a single grid. part receives
 // one FP64 partial per tile (tile_counts(...).tiles() of them).

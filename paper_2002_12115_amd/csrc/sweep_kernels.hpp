@@ -583,6 +583,148 @@ __global__ __launch_bounds__(kWave * (BJ + 2)) void fused_kernel(Grid<T> g, T om
     if (threadIdx.x == 0) part2[L] = acc2;
 }
 
+// ---- flat kernel: tiles of consecutive interior (j,k) cells -------------------
+//
+// A tile is a run of T = 64*NW consecutive cells of the flattened interior
+// (j,k) plane (cell c: j = 1 + c / (nz-2), k = 1 + c % (nz-2)), so no lane
+// idles at the end of a k row, whatever nz is. The workgroup marches along
+// i; each plane's rows j-1 .. j+1 of the tile are staged in LDS compactly
+// (nz values per row, no padding) in a 4-slot ring, and every neighbour is
+// at +-1, +-nz or +-nz+-1 there. Usable while (rows touched) x nz fits
+// kFlatPlaneBytes.
+constexpr int kFlatPlaneBytes = 10240;
+
+template <typename T, int NW>
+struct alignas(16) FlatLds {
+    static constexpr int CAP = kFlatPlaneBytes / (int)sizeof(T);   // elements per plane
+    static constexpr int NT = kWave * NW;
+    static constexpr int PREF = (CAP + NT - 1) / NT;               // staged values per thread
+    T ring[4][CAP];
+    double red[NW];
+};
+
+// Rows of the interior plane a tile of T cells starting at cell c0 touches,
+// plus the halo row above and below.
+__host__ __device__ inline int flat_rows(int c0, int ncells_tile, int nzi)
+{
+    const int c1 = c0 + ncells_tile - 1;
+    return c1 / nzi - c0 / nzi + 3;
+}
+
+template <typename T, int NW>
+struct FlatRegs {
+    T v[FlatLds<T, NW>::PREF];
+};
+
+// Fetch rows jr0 .. jr0+nrows-1 (k = 0 .. nz-1) of plane ii.
+template <typename T, int NW>
+__device__ __forceinline__ void flat_fetch(const Grid<T>& g, int ii, int jr0, int n, FlatRegs<T, NW>& r)
+{
+    constexpr int NT = FlatLds<T, NW>::NT;
+    const T* base = g.src + (long long)ii * g.S + (long long)jr0 * g.P;
+    int e = threadIdx.x;
+    int row = e / g.nz, k = e - row * g.nz;
+    const int drow = NT / g.nz, dk = NT - drow * g.nz;
+#pragma unroll
+    for (int m = 0; m < FlatLds<T, NW>::PREF; ++m) {
+        if (e < n) r.v[m] = base[(long long)row * g.P + k];
+        e += NT;
+        row += drow;
+        k += dk;
+        if (k >= g.nz) {
+            k -= g.nz;
+            ++row;
+        }
+    }
+}
+
+template <typename T, int NW>
+__device__ __forceinline__ void flat_put(T* pl, int n, const FlatRegs<T, NW>& r)
+{
+    constexpr int NT = FlatLds<T, NW>::NT;
+    int e = threadIdx.x;
+#pragma unroll
+    for (int m = 0; m < FlatLds<T, NW>::PREF; ++m) {
+        if (e < n) pl[e] = r.v[m];
+        e += NT;
+    }
+}
+
+template <typename T, int NW, bool NT_, bool WRITE>
+__device__ __forceinline__ void flat_tile(const Grid<T>& g, T omega, int c0, int ib, int ie,
+                                          FlatLds<T, NW>& sm, double& acc)
+{
+    constexpr int NT = FlatLds<T, NW>::NT;
+    const int nzi = g.nz - 2;
+    const int ncell = (g.ny - 2) * nzi;
+    const int tcells = (ncell - c0 < NT) ? (ncell - c0) : NT;
+    const int jr0 = c0 / nzi;                          // first staged row: (1 + c0/nzi) - 1
+    const int nrows = flat_rows(c0, tcells, nzi);
+    const int n = nrows * g.nz;                        // staged elements per plane
+    const int c = c0 + (int)threadIdx.x;
+    const bool active = (int)threadIdx.x < tcells;
+    const int j = 1 + c / nzi, k = 1 + c % nzi;
+    const int ctr = (j - jr0) * g.nz + k;              // the cell's position in a staged plane
+    const int rs = g.nz;                               // row stride in LDS
+    const long long rowoff = (long long)j * g.P + k;
+
+    FlatRegs<T, NW> rr;
+    for (int ii = ib - 1; ii <= ib + 1; ++ii) {
+        flat_fetch<T, NW>(g, ii, jr0, n, rr);
+        flat_put<T, NW>(sm.ring[ii & 3], n, rr);
+    }
+    __syncthreads();
+
+    for (int i = ib; i < ie; ++i) {
+        const bool more = (i + 1 < ie);
+        if (more) flat_fetch<T, NW>(g, i + 2, jr0, n, rr);
+        if (active) {
+            const long long o = (long long)i * g.S + rowoff;
+            T cf[NCOEF];
+#pragma unroll
+            for (int q = 0; q < NCOEF; ++q) cf[q] = sload<T, NT_>(g.coef[q] + o);
+            const T* Pm = sm.ring[(i - 1) & 3] + ctr;
+            const T* Pc = sm.ring[i & 3] + ctr;
+            const T* Pp = sm.ring[(i + 1) & 3] + ctr;
+            const T pc = Pc[0];
+            const T ss = cell_ss<T>(cf[CA0], cf[CA1], cf[CA2], cf[CA3], cf[CB0], cf[CB1], cf[CB2], cf[CC0],
+                                    cf[CC1], cf[CC2], cf[CBND], cf[CWRK1],
+                                    Pp[0], Pc[rs], Pc[1],
+                                    bracket(Pp[rs], Pp[-rs], Pm[rs], Pm[-rs]),
+                                    bracket(Pc[rs + 1], Pc[-rs + 1], Pc[rs - 1], Pc[-rs - 1]),
+                                    bracket(Pp[1], Pm[1], Pp[-1], Pm[-1]),
+                                    Pm[0], Pc[-rs], Pc[-1], pc);
+            if constexpr (WRITE) {
+                const T outv = pc + omega * ss;
+                if constexpr (NT_) __builtin_nontemporal_store(outv, g.dst + o);
+                else g.dst[o] = outv;
+            }
+            const double d = (double)ss;
+            acc += d * d;
+        }
+        if (more) flat_put<T, NW>(sm.ring[(i + 2) & 3], n, rr);
+        __syncthreads();
+    }
+}
+
+template <typename T, int NW, bool NT_, bool WRITE>
+__global__ __launch_bounds__(kWave * NW) void flat_kernel(Grid<T> g, T omega, int ichunk, int ct_n, int remap,
+                                                          double* __restrict__ part)
+{
+    __shared__ FlatLds<T, NW> sm;
+    const int nb = gridDim.x;
+    const int L = remap_xcd(blockIdx.x, nb, remap);
+    const int ct = L % ct_n;
+    const int ic = L / ct_n;
+    const int ib = 1 + ic * ichunk;
+    int ie = ib + ichunk;
+    if (ie > g.nx - 1) ie = g.nx - 1;
+    double acc = 0.0;
+    flat_tile<T, NW, NT_, WRITE>(g, omega, ct * kWave * NW, ib, ie, sm, acc);
+    acc = block_sum<NW>(acc, sm.red);
+    if (threadIdx.x == 0) part[L] = acc;
+}
+
 // ---- batch: many grids, one launch over a flattened tile list ---------------
 
 
@@ -613,6 +755,36 @@ __global__ __launch_bounds__(kWave * BJ) void batch_kernel(const Instance<T>* __
         double acc = 0.0;
         march_tile<T, BJ, V, NT, WRITE>(g, omega, kt, jt, ib, ie, sm, acc);
         acc = block_sum<BJ>(acc, sm.red);
+        if (threadIdx.x == 0) part[L] = acc;
+        __syncthreads();
+    }
+}
+
+// The flat tiles of many grids in one launch (instance descriptors as for
+// batch_kernel; kt_n holds the instance's number of flat tiles per i-chunk).
+template <typename T, int NW, bool NT_, bool WRITE>
+__global__ __launch_bounds__(kWave * NW) void flat_batch_kernel(const Instance<T>* __restrict__ inst,
+                                                                const int* __restrict__ tile_inst, int ntiles,
+                                                                int parity, T omega, double* __restrict__ part)
+{
+    __shared__ FlatLds<T, NW> sm;
+    for (int L = blockIdx.x; L < ntiles; L += gridDim.x) {
+        const Instance<T>& d = inst[tile_inst[L]];
+        Grid<T> g;
+#pragma unroll
+        for (int q = 0; q < NCOEF; ++q) g.coef[q] = d.coef[q];
+        g.src = d.f[parity];
+        g.dst = d.f[parity ^ 1];
+        g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.P = d.P; g.S = d.S;
+        const int t = L - d.tile0;
+        const int ct = t % d.kt_n;
+        const int ic = t / d.kt_n;
+        const int ib = 1 + ic * d.ichunk;
+        int ie = ib + d.ichunk;
+        if (ie > g.nx - 1) ie = g.nx - 1;
+        double acc = 0.0;
+        flat_tile<T, NW, NT_, WRITE>(g, omega, ct * kWave * NW, ib, ie, sm, acc);
+        acc = block_sum<NW>(acc, sm.red);
         if (threadIdx.x == 0) part[L] = acc;
         __syncthreads();
     }

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhj.so")
 
 F64, F32 = 0, 1
-KERNEL_DIRECT, KERNEL_MARCH = 0, 1
+KERNEL_DIRECT, KERNEL_MARCH, KERNEL_FLAT = 0, 1, 2
 STATUS = {0: "HJ_OK", -1: "HJ_ERR_ARG", -2: "HJ_ERR_SHAPE", -3: "HJ_ERR_DTYPE", -4: "HJ_ERR_OOM",
           -5: "HJ_ERR_HIP", -6: "HJ_ERR_STATE", -7: "HJ_ERR_HANDLE", -8: "HJ_ERR_TUNE"}
 

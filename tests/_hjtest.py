@@ -31,11 +31,17 @@ def gosa_err(g, ref):
 
 def gpu_run(shape, dtype, n_iter, omega=0.8, seed=2002, cfg=None, bnd_mode=0, use_torch=None,
             arrays=None):
-    """(p, gosa_hist, solver config) from the HIP path."""
+    """(p, gosa_hist, solver config) from the HIP path, or None when the
+    configuration cannot run this grid (a flat kernel too wide for it)."""
     f = arrays if arrays is not None else inputs.fields(seed, shape, bnd_mode=bnd_mode)
     with hj.Solver(dtype, shape, use_torch=use_torch) as s:
         if cfg is not None:
-            s.config = cfg
+            try:
+                s.config = cfg
+            except hj.HJError as e:
+                if cfg.kernel == hj.KERNEL_FLAT and e.status == -1:
+                    return None
+                raise
         s.upload_all(f)
         s.sweep(n_iter, omega)
         p = s.download("p")
@@ -65,6 +71,16 @@ def f64_configs():
             for ich, nt, rm in ((1, 1, 0), (3, 0, 1), (16, 1, 1), (1000, 0, 0)):
                 out.append(cfg(bj=bj, vec=v, ichunk=ich, nontemporal=nt, xcd_remap=rm))
     out.extend(fused_configs())
+    out.extend(flat_configs())
+    return out
+
+
+def flat_configs():
+    """Runs of consecutive interior (j,k) cells."""
+    out = []
+    for nw in (2, 4, 8):
+        for ich, nt, rm in ((1, 1, 0), (3, 0, 1), (1000, 1, 1)):
+            out.append(cfg(kernel=hj.KERNEL_FLAT, bj=nw, vec=1, ichunk=ich, nontemporal=nt, xcd_remap=rm))
     return out
 
 
@@ -84,10 +100,12 @@ def f32_configs():
             for ich, nt, rm in ((2, 1, 1), (7, 0, 0)):
                 out.append(cfg(bj=bj, vec=v, ichunk=ich, nontemporal=nt, xcd_remap=rm))
     out.extend(fused_configs())
+    out.extend(flat_configs())
     return out
 
 
 def cfg_id(c):
     d = c.as_dict()
-    k = "direct" if d["kernel"] == 0 else ("fused%d" % d["reread"] if d["tsteps"] == 2 else "march")
+    k = ("direct" if d["kernel"] == 0 else "flat" if d["kernel"] == 2 else
+         "fused%d" % d["reread"] if d["tsteps"] == 2 else "march")
     return "%s-bj%d-v%d-ic%d-nt%d-rm%d" % (k, d["bj"], d["vec"], d["ichunk"], d["nontemporal"], d["xcd_remap"])

@@ -171,7 +171,7 @@ def test_gene_decoding(lib):
             for g in range(2 ** 11):
                 d = dec(dtype, g, batch)
                 if batch:
-                    assert d["kernel"] == 1 and d["tsteps"] == 1 and d["xcd_remap"] == 0
+                    assert d["kernel"] in (1, 2) and d["tsteps"] == 1 and d["xcd_remap"] == 0
     # folded codes: vec code 2 is 1 for FP64 and 4 for FP32; direct reads bj 1 as 2
     assert dec(0, 1 | (2 << 3))["vec"] == 1 and dec(1, 1 | (2 << 3))["vec"] == 4
     assert dec(0, 0)["bj"] == 2 and dec(0, 0)["kernel"] == 0
@@ -179,10 +179,14 @@ def test_gene_decoding(lib):
     d = dec(0, 1 | (1 << 10) | (3 << 3))
     assert (d["tsteps"], d["vec"], d["bj"], d["reread"]) == (2, 1, 14, 1)
     assert dec(0, 1 | (1 << 10) | (2 << 3))["reread"] == 0
-    assert dec(0, 1 << 10)["tsteps"] == 1              # bit 10 is ignored by the direct kernel
+    d = dec(0, 1 << 10)                                 # bit 0 clear, bit 10 set: the flat kernel
+    assert (d["kernel"], d["tsteps"], d["bj"]) == (2, 1, 2)
+    # a flat run too wide for the grid folds onto the march kernel
+    assert dec(0, (1 << 10) | (3 << 1), shape=(5, 6, 900))["kernel"] == 1
     # batch: bit 9 is the persistent grid, the chunk is 2^(bits 5-7)
     d = dec(1, 1 | (1 << 1) | (3 << 5) | (1 << 9), batch=1, shape=(0, 0, 0))
-    assert (d["persistent"], d["ichunk"], d["xcd_remap"]) == (1, 8, 0)
+    assert (d["kernel"], d["persistent"], d["ichunk"], d["xcd_remap"]) == (1, 1, 8, 0)
+    assert dec(1, (2 << 1) | (2 << 5), batch=1, shape=(0, 0, 0))["kernel"] == 2
     # chunk choices shrink as the workgroup target grows
     ch = [dec(0, 1 | (2 << 1) | (sel << 5))["ichunk"] for sel in range(8)]
     assert ch == sorted(ch, reverse=True) and ch[-1] == 1

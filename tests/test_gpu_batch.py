@@ -18,6 +18,10 @@ def small_batch(seed=2002, n=7):
 
 def batch_configs(dtype):
     out = []
+    for nw in (2, 4, 8):
+        for ich, nt, per in ((1, 1, 0), (5, 0, 1)):
+            out.append(hj.Config.make(kernel=2, bj=nw, vec=1, ichunk=ich, nontemporal=nt, use_graph=1, xcd_remap=0,
+                                      persistent=per))
     vmax = 2 if dtype == "f64" else 4
     for bj in (1, 2, 4, 8):
         v = 1
@@ -99,6 +103,11 @@ def test_batch_errors():
         with pytest.raises(hj.HJError):
             b.config = hj.Config.make(kernel=0, bj=4, vec=1, ichunk=4, nontemporal=0, use_graph=1,
                                       xcd_remap=0, persistent=0)
+    with hj.Batch("f64", [(4, 4, 4), (5, 6, 900)]) as b:
+        with pytest.raises(hj.HJError) as e:      # a flat run too wide for one instance
+            b.config = hj.Config.make(kernel=2, bj=8, vec=1, ichunk=4, nontemporal=0, use_graph=1,
+                                      xcd_remap=0, persistent=0)
+        assert e.value.status == -1
         with pytest.raises(ValueError):
             b.upload(1, "p", np.zeros((4, 4, 4)))
 
