@@ -127,16 +127,17 @@ def values(seed: int, name, shape: Sequence[int], idx, sigma: float = DEFAULT_SI
 
 
 def neighbourhood(seed: int, shape: Sequence[int], centres, sigma: float = DEFAULT_SIGMA,
-                  bnd_mode: int = 0, dtype=np.float64) -> Dict[str, np.ndarray]:
-    """The 13 inputs on the 3x3x3 block around each interior centre (i,j,k).
+                  bnd_mode: int = 0, dtype=np.float64, radius: int = 1) -> Dict[str, np.ndarray]:
+    """The 13 inputs on the (2r+1)^3 block around each centre (i,j,k).
 
-    Returns arrays of shape [m, 3, 3, 3]; block q holds cells (i-1..i+1,
-    j-1..j+1, k-1..k+1) of centre q, with the values the full grid has there
-    (rounded to `dtype`, then widened back to FP64).
+    Returns arrays of shape [m, 2r+1, 2r+1, 2r+1]; block q holds cells
+    (i-r..i+r, j-r..j+r, k-r..k+r) of centre q, with the values the full
+    grid has there (rounded to `dtype`, then widened back to FP64). Every
+    block must lie inside the grid.
     """
     nx, ny, nz = (int(s) for s in shape)
     c = np.asarray(centres, dtype=np.int64).reshape(-1, 3)
-    d = np.arange(-1, 2)
+    d = np.arange(-radius, radius + 1)
     ii = c[:, 0, None, None, None] + d[None, :, None, None]
     jj = c[:, 1, None, None, None] + d[None, None, :, None]
     kk = c[:, 2, None, None, None] + d[None, None, None, :]

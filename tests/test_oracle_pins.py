@@ -329,3 +329,16 @@ def test_neighbourhood_blocks_reproduce_full_sweep():
     for q, (i, j, k) in enumerate(cells):
         blk = {n: nb[n][q] for n in inputs.INPUTS}
         assert oracle.sweep(blk, 1, 0.8)[0][1, 1, 1] == p1[i, j, k]
+
+
+def test_radius_two_blocks_reproduce_two_sweeps():
+    """After two Jacobi iterations a cell depends only on its 5x5x5 block."""
+    shape = (11, 12, 13)
+    f = inputs.fields(7, shape)
+    p2, _, _ = oracle.sweep(f, 2, 0.8)
+    rng = np.random.default_rng(2)
+    cells = np.stack([rng.integers(2, s - 2, 30) for s in shape], 1)
+    nb = inputs.neighbourhood(7, shape, cells, radius=2)
+    for q, (i, j, k) in enumerate(cells):
+        blk = {n: nb[n][q] for n in inputs.INPUTS}
+        assert oracle.sweep(blk, 2, 0.8)[0][2, 2, 2] == p2[i, j, k]
