@@ -79,7 +79,7 @@ enum hj_field {
  * tsteps: Jacobi iterations per pass over memory (single solves). 1, or 2:
  * the march kernel computes the first iteration of a tile and its one-cell
  * halo into LDS and the second from it, so each coefficient is read once
- * per two iterations (needs kernel HJ_KERNEL_MARCH, vec 1, bj 2, 4, 8 or 14;
+ * per two iterations (needs kernel HJ_KERNEL_MARCH, vec 1, bj 2, 4, 6, 8 or 14;
  * an odd remainder runs one single-iteration launch). 0 means 1. The
  * results are bitwise those of tsteps 1.
  * reread (tsteps 2 only): 0 holds each cell's coefficients in registers
@@ -176,12 +176,19 @@ int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long l
                    double pm, int n_sweeps, int repeats, hj_config* best, double* best_ms,
                    int* evaluations);
 
-/* The configuration a gene names for this problem. bits 1-2: bj 1, 2, 4, 8
- * (the direct kernel reads 1 as 2, two-iteration passes read it as 14);
- * bits 3-4: vec 1, 2, 1, 2 (FP64) or 1, 2, 4, 4 (FP32) for the one-iteration
- * march kernel, and bit 3 is reread for two-iteration passes; bits 5-7 pick the i-chunk giving about 512 << n workgroups
- * (64 << n for two-iteration passes; 2^n for batches). batch != 0: for a
- * batch, always the march kernel, bit 9 the persistent grid, bit 10 unused. */
+/* The configuration a gene names for this problem; every gene names one.
+ * bit 0: direct (0) or march (1) kernel; with bit 10 set, flat (0) or march
+ * with two iterations per pass (1). bits 1-2: bj 1, 2, 4, 8 (the direct
+ * kernel reads 1 as 2; two-iteration passes read the codes as 14, 6, 4, 8).
+ * bits 3-4: vec 1, 2, 1, 2 (FP64) or 1, 2, 4, 4 (FP32) for the
+ * one-iteration march kernel; bit 3 is reread for two-iteration passes.
+ * bits 5-7: the i-chunk n, giving about 512 << n workgroups; for
+ * two-iteration passes the longest chunk within 256, 512, 768, 1024, 2048,
+ * 4096, 8192 or 24576 workgroups; 2^n planes for batches. bit 8:
+ * nontemporal. bit 9: xcd_remap (single solves), persistent (batches).
+ * batch != 0: bit 0 picks flat (0) or march (1), bit 10 is unused. A flat
+ * kernel that does not fit the grid reads as the march kernel. Returns
+ * HJ_ERR_ARG for an unknown dtype. Host only. */
 int hj_gene_config(int dtype, int nx, int ny, int nz, int batch, unsigned gene, hj_config* out);
 
 /* The same genetic search with the time of every gene given by a table

@@ -158,6 +158,18 @@ int ichunk_for(const hj_config& c, int nx, int ny, int nz, long long target)
     return (int)std::max<long long>(1, (nx - 2 + nchunks - 1) / nchunks);
 }
 
+// The longest i-chunk that keeps the grid within max_wg workgroups (whole
+// waves of resident workgroups leave no CU idle in a last, partial wave).
+int ichunk_within(const hj_config& c, int nx, int ny, int nz, long long max_wg)
+{
+    hj_config u = c;
+    u.ichunk = 1;
+    const TileCounts one = tile_counts(u, nx, ny, nz);
+    const long long base = std::max<long long>(1, (long long)one.kt_n * one.jt_n);
+    const long long nchunks = std::max<long long>(1, max_wg / base);
+    return (int)std::max<long long>(1, (nx - 2 + nchunks - 1) / nchunks);
+}
+
 // Reference configuration of the autotuner's parity gate: the plainest kernel.
 hj_config reference_config(int dtype)
 {
@@ -492,7 +504,7 @@ struct Evaluator {
 // mode are ignored, unusable ones fold onto usable ones):
 //   bit 0      kernel: 0 direct, 1 march; with bit 10: 0 flat, 1 march with
 //              two iterations per pass (batches: 0 flat, 1 march)
-//   bits 1-2   bj: 1, 2, 4, 8 (direct: 1 reads as 2; two-iteration: 1 reads as 14)
+//   bits 1-2   bj: 1, 2, 4, 8 (direct: 1 reads as 2; two-iteration: 14, 6, 4, 8)
 //   bits 3-4   vec (march, one iteration): FP64 1, 2, 1, 2; FP32 1, 2, 4, 4;
 //              bit 3 is reread for two-iteration passes
 //   bits 5-7   one of 8 i-chunk lengths (march kernels)
@@ -503,17 +515,20 @@ struct Evaluator {
 constexpr int kGeneBits = 11;
 
 // The 8 i-chunk lengths a gene can name for one grid: the chunk that gives
-// about 512, 1024, ..., 65536 workgroups (64 .. 8192 for two-iteration passes,
-// whose chunks recompute their halo planes).
+// about 512, 1024, ..., 65536 workgroups; for two-iteration passes, whose
+// chunks recompute their halo planes and whose workgroups are few and long,
+// the longest chunk within 256, 512, 768, 1024, 2048, 4096, 8192 or 24576
+// workgroups (whole waves on a chip of 256 CUs).
 int gene_ichunk(int sel, const hj_config& c, int nx, int ny, int nz)
 {
-    const long long target = fused_of(c) ? (64LL << sel) : (512LL << sel);
-    return ichunk_for(c, nx, ny, nz, target);
+    static const long long kFusedWg[8] = {256, 512, 768, 1024, 2048, 4096, 8192, 24576};
+    if (fused_of(c)) return ichunk_within(c, nx, ny, nz, kFusedWg[sel & 7]);
+    return ichunk_for(c, nx, ny, nz, 512LL << sel);
 }
 
 bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_config& c)
 {
-    static const int kBj[4] = {1, 2, 4, 8};
+    static const int kBj[4] = {1, 2, 4, 8}, kBjFused[4] = {14, 6, 4, 8};
     static const int kVec64[4] = {1, 2, 1, 2}, kVec32[4] = {1, 2, 4, 4};
     c = default_config(dtype);
     const int b0 = g & 1, b10 = (g >> 10) & 1;
@@ -539,7 +554,7 @@ bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_c
         c.vec = 1;
         c.ichunk = 1;
     } else if (c.tsteps == 2) {
-        if (c.bj == 1) c.bj = 14;
+        c.bj = kBjFused[bi];
         c.vec = 1;
         c.reread = vi & 1;
         c.ichunk = gene_ichunk(sel, c, nx, ny, nz);
@@ -858,7 +873,9 @@ int validate_config(int dtype, const hj_config* c)
 }
 
 // Candidate configurations of the autotuner for one grid.
-std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch)
+// The autotuner's candidates for one grid; cus is the device's CU count
+// (two-iteration chunks are sized to whole waves of resident workgroups).
+std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch, int cus)
 {
     std::vector<hj_config> out;
     const hj_config base = default_config(dtype);
@@ -918,24 +935,30 @@ std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch)
                     for (const hj_config& y : out) dup = dup || same_config(x, y);
                     if (!dup && config_fits(dtype, x, nx, ny, nz)) out.push_back(x);
                 }
-        // two iterations per pass: long chunks (the halo planes of a chunk are recomputed)
-        for (int bj : {4, 8, 14})
-            for (int target : {128, 256, 512, 1024, 2048, 4096})
-                for (int nt : {0, 1})
-                    for (int rr : {0, 1}) {
-                        hj_config x = base;
-                        x.kernel = HJ_KERNEL_MARCH;
-                        x.bj = bj;
-                        x.vec = 1;
-                        x.tsteps = 2;
-                        x.reread = rr;
-                        x.nontemporal = nt;
-                        x.xcd_remap = 0;
-                        x.ichunk = ichunk_for(x, nx, ny, nz, target);
+        // two iterations per pass: long chunks (the halo planes of a chunk are
+        // recomputed), sized to 1 .. 64 waves of resident workgroups; XCD
+        // renumbering lets neighbouring tiles share their halo reads in L2
+        for (int bj : {6, 8, 14})
+            for (int rr : {0, 1})
+                for (int rm : {0, 1}) {
+                    hj_config x = base;
+                    x.kernel = HJ_KERNEL_MARCH;
+                    x.bj = bj;
+                    x.vec = 1;
+                    x.tsteps = 2;
+                    x.reread = rr;
+                    x.nontemporal = 0;
+                    x.xcd_remap = rm;
+                    if (!config_supported(dtype, x)) continue;
+                    const int occ = dtype == HJ_F64 ? fused_occupancy<double>(x) : fused_occupancy<float>(x);
+                    const long long cap = (long long)std::max(occ, 1) * std::max(cus, 1);
+                    for (int m : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64}) {
+                        x.ichunk = ichunk_within(x, nx, ny, nz, m * cap);
                         bool dup = false;
                         for (const hj_config& y : out) dup = dup || same_config(x, y);
-                        if (!dup && config_supported(dtype, x)) out.push_back(x);
+                        if (!dup) out.push_back(x);
                     }
+                }
     }
     return out;
 }
@@ -1229,7 +1252,10 @@ int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double*
         tu.ev.eval(reference_config(h->dtype));  // the parity reference (also a contender below)
         hj_config win = tu.keep;
         double win_ms = INFINITY;
-        for (const hj_config& c : candidates(h->dtype, h->L.nx, h->L.ny, h->L.nz, false)) {
+        int dev = 0, cus = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        for (const hj_config& c : candidates(h->dtype, h->L.nx, h->L.ny, h->L.nz, false, cus)) {
             const double ms = tu.ev.eval(c);
             if (ms < win_ms) {
                 win_ms = ms;

@@ -119,7 +119,7 @@ bool config_supported(int dtype, const hj_config& c)
     if (c.xcd_remap < 0 || c.xcd_remap > 1) return false;
     if (c.tsteps == 2)
         return c.kernel == HJ_KERNEL_MARCH && c.vec == 1 && c.ichunk >= 1 && c.persistent == 0 &&
-               (c.bj == 2 || c.bj == 4 || c.bj == 8 || c.bj == 14);
+               (c.bj == 2 || c.bj == 4 || c.bj == 6 || c.bj == 8 || c.bj == 14);
     if (c.kernel == HJ_KERNEL_FLAT) return (c.bj == 2 || c.bj == 4 || c.bj == 8) && c.vec == 1 && c.ichunk >= 1;
     if (!bj_ok(c.bj)) return false;
     if (c.kernel == HJ_KERNEL_DIRECT) return c.bj >= 2;
@@ -273,7 +273,41 @@ hipError_t fused_bj(const hj_config& c, const Grid<T>& g, T omega, double* part1
                          : fused_go<T, BJ, false, true>(c, g, omega, part1, part2, st);
 }
 
+template <typename T, int BJ, bool NT, bool KEEP>
+int fused_occ()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_kernel<T, BJ, NT, KEEP>, kWave * (BJ + 2), 0) !=
+        hipSuccess)
+        return 0;
+    return n;
+}
+
+template <typename T, int BJ>
+int fused_occ_bj(const hj_config& c)
+{
+    if (c.reread) return c.nontemporal ? fused_occ<T, BJ, true, false>() : fused_occ<T, BJ, false, false>();
+    return c.nontemporal ? fused_occ<T, BJ, true, true>() : fused_occ<T, BJ, false, true>();
+}
+
 }  // namespace
+
+template <typename T>
+int fused_occupancy(const hj_config& c)
+{
+    if (!fused_of(c)) return 0;
+    switch (c.bj) {
+    case 2: return fused_occ_bj<T, 2>(c);
+    case 4: return fused_occ_bj<T, 4>(c);
+    case 6: return fused_occ_bj<T, 6>(c);
+    case 8: return fused_occ_bj<T, 8>(c);
+    case 14: return fused_occ_bj<T, 14>(c);
+    default: return 0;
+    }
+}
+
+template int fused_occupancy<double>(const hj_config&);
+template int fused_occupancy<float>(const hj_config&);
 
 template <typename T>
 hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
@@ -283,6 +317,7 @@ hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* p
     switch (c.bj) {
     case 2: return fused_bj<T, 2>(c, g, omega, part1, part2, st);
     case 4: return fused_bj<T, 4>(c, g, omega, part1, part2, st);
+    case 6: return fused_bj<T, 6>(c, g, omega, part1, part2, st);
     case 8: return fused_bj<T, 8>(c, g, omega, part1, part2, st);
     case 14: return fused_bj<T, 14>(c, g, omega, part1, part2, st);
     default: return hipErrorInvalidValue;

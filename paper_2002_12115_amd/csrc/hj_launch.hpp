@@ -73,6 +73,11 @@ template <typename T>
 hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                         hipStream_t st);
 
+// Workgroups of the two-iteration kernel named by c resident per CU (0 when
+// c names none, or the query fails).
+template <typename T>
+int fused_occupancy(const hj_config& c);
+
 // One iteration over every instance of a batch.
 template <typename T>
 hipError_t launch_batch(const hj_config& c, const Instance<T>* inst, const int* tile_inst,

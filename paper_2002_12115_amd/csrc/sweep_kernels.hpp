@@ -561,7 +561,7 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
 }
 
 template <typename T, int BJ, bool NT, bool KEEP>
-__global__ __launch_bounds__(kWave * (BJ + 2)) void fused_kernel(Grid<T> g, T omega, int ichunk, int kt_n,
+__global__ __launch_bounds__(kWave * (BJ + 2)) __attribute__((amdgpu_waves_per_eu(BJ == 6 ? 4 : 1))) void fused_kernel(Grid<T> g, T omega, int ichunk, int kt_n,
                                                                   int jt_n, int remap,
                                                                   double* __restrict__ part1,
                                                                   double* __restrict__ part2)

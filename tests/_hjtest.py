@@ -87,7 +87,7 @@ def flat_configs():
 def fused_configs():
     """Two iterations per pass (tsteps 2)."""
     out = []
-    for bj in (2, 4, 8, 14):
+    for bj in (2, 4, 6, 8, 14):
         for ich, nt, rm, rr in ((1, 1, 0, 0), (2, 0, 1, 1), (5, 1, 0, 1), (1000, 0, 1, 0)):
             out.append(cfg(bj=bj, vec=1, ichunk=ich, nontemporal=nt, xcd_remap=rm, tsteps=2, reread=rr))
     return out

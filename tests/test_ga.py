@@ -175,10 +175,16 @@ def test_gene_decoding(lib):
     # folded codes: vec code 2 is 1 for FP64 and 4 for FP32; direct reads bj 1 as 2
     assert dec(0, 1 | (2 << 3))["vec"] == 1 and dec(1, 1 | (2 << 3))["vec"] == 4
     assert dec(0, 0)["bj"] == 2 and dec(0, 0)["kernel"] == 0
-    # two iterations per pass: march only, vec 1, bj code 0 reads as 14
+    # two iterations per pass: march only, vec 1, bj codes read as 14, 6, 4, 8
     d = dec(0, 1 | (1 << 10) | (3 << 3))
     assert (d["tsteps"], d["vec"], d["bj"], d["reread"]) == (2, 1, 14, 1)
     assert dec(0, 1 | (1 << 10) | (2 << 3))["reread"] == 0
+    assert [dec(0, 1 | (1 << 10) | (b << 1))["bj"] for b in range(4)] == [14, 6, 4, 8]
+    # their chunks: the longest within 256, 512, ... workgroups (5 x 16 tiles of bj 8 here)
+    fch = [dec(0, 1 | (1 << 10) | (3 << 1) | (sel << 5))["ichunk"] for sel in range(8)]
+    assert fch[:4] == [43, 22, 15, 11]
+    for sel, wg in enumerate((256, 512, 768, 1024, 2048, 4096, 8192, 24576)):
+        assert 80 * -(-128 // fch[sel]) <= wg
     d = dec(0, 1 << 10)                                 # bit 0 clear, bit 10 set: the flat kernel
     assert (d["kernel"], d["tsteps"], d["bj"]) == (2, 1, 2)
     # a flat run too wide for the grid folds onto the march kernel
