@@ -184,11 +184,13 @@ int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long l
  * one-iteration march kernel; bit 3 is reread for two-iteration passes.
  * bits 5-7: the i-chunk n, giving about 512 << n workgroups; for
  * two-iteration passes the longest chunk within 256, 512, 768, 1024, 2048,
- * 4096, 8192 or 24576 workgroups; 2^n planes for batches. bit 8:
- * nontemporal. bit 9: xcd_remap (single solves), persistent (batches).
- * batch != 0: bit 0 picks flat (0) or march (1), bit 10 is unused. A flat
- * kernel that does not fit the grid reads as the march kernel. Returns
- * HJ_ERR_ARG for an unknown dtype. Host only. */
+ * 4096, 8192 or 24576 workgroups; for batches 2^n planes (one-iteration)
+ * or 4 * 2^n planes (two-iteration). bit 8: nontemporal. bit 9: xcd_remap
+ * (single solves and two-iteration batches), persistent (one-iteration
+ * batches). batch != 0: bit 0 picks flat (0) or march (1), and bit 10 with
+ * bit 0 two iterations per pass. A flat kernel that does not fit the grid
+ * reads as the march kernel. Returns HJ_ERR_ARG for an unknown dtype.
+ * Host only. */
 int hj_gene_config(int dtype, int nx, int ny, int nz, int batch, unsigned gene, hj_config* out);
 
 /* The same genetic search with the time of every gene given by a table
@@ -210,8 +212,9 @@ int hj_destroy(hj_solver h);
 /* ---- batch of independent solves ---------------------------------------- */
 
 /* n solves of individual shapes, all in one device slab, advanced together:
- * each iteration is one launch over a flattened list of every instance's
- * tiles, and the loop is replayed as a captured HIP graph. */
+ * each pass is one launch over a flattened list of every instance's tiles
+ * (one iteration, or two with tsteps 2, where an odd remainder runs one
+ * one-iteration pass), and the loop is replayed as a captured HIP graph. */
 int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* ny,
                     const int* nz, void* stream);
 int hj_batch_upload(hj_batch b, int inst, int field, const void* host_src);
@@ -223,10 +226,13 @@ int hj_batch_download(hj_batch b, int inst, int field, void* host_dst);
 int hj_batch_sweep(hj_batch b, int n_iter, double omega, double* gosa_last, double* gosa_hist);
 int hj_batch_residual(hj_batch b, double* gosa);
 int hj_batch_get_config(hj_batch b, hj_config* out);
+/* Any supported configuration but the direct kernel; a flat kernel must fit
+ * every instance (else HJ_ERR_ARG). xcd_remap and reread are kept for
+ * two-iteration passes (tsteps 2, not persistent) and cleared otherwise. */
 int hj_batch_set_config(hj_batch b, const hj_config* cfg);
 int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, double* best_ms);
-/* Genetic search over the batch's configuration (as hj_autotune_ga; bit 9
- * selects the persistent grid, the i-chunk is 2^(bits 5-7)). */
+/* Genetic search over the batch's configuration (as hj_autotune_ga, with
+ * the batch reading of the gene that hj_gene_config documents). */
 int hj_batch_autotune_ga(hj_batch b, int population, int generations, unsigned long long seed, double pc,
                          double pm, int n_sweeps, int repeats, hj_config* best, double* best_ms,
                          int* evaluations);

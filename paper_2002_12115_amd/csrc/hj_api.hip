@@ -440,7 +440,8 @@ struct TuneOps {
     std::function<void(const hj_config&)> set;     // select a configuration (may throw)
     std::function<void()> restore;                 // back to the saved state
     std::function<void(int)> run;                  // enqueue n sweeps
-    std::function<std::pair<const void*, size_t>()> result;  // bytes the parity gate compares
+    // the device regions the parity gate compares (the current p of each grid)
+    std::function<std::vector<std::pair<const void*, size_t>>()> result;
 };
 
 // Times configurations on the caller's arrays. The first configuration
@@ -465,16 +466,28 @@ struct Evaluator {
             tune_log(kind, dtype, nx, ny, nz, c, INFINITY, "launch-failed");
             return INFINITY;  // a candidate that does not launch is never chosen
         }
-        const std::pair<const void*, size_t> res = ops.result();
+        const std::vector<std::pair<const void*, size_t>> res = ops.result();
         if (!have_ref) {
-            ref.ensure(res.second);
-            HIPCHK(hipMemcpyAsync(ref.p, res.first, res.second, hipMemcpyDeviceToDevice, ops.st));
+            size_t total = 0;
+            for (const auto& r : res) total += r.second;
+            ref.ensure(total);
+            size_t o = 0;
+            for (const auto& r : res) {
+                HIPCHK(hipMemcpyAsync(static_cast<char*>(ref.p) + o, r.first, r.second, hipMemcpyDeviceToDevice,
+                                      ops.st));
+                o += r.second;
+            }
             have_ref = true;
         } else {
             unsigned long long bad = 0;
             cnt.ensure(8);
             HIPCHK(hipMemcpyAsync(cnt.p, &bad, 8, hipMemcpyHostToDevice, ops.st));
-            HIPCHK(launch_diff(res.first, ref.p, res.second, static_cast<unsigned long long*>(cnt.p), ops.st));
+            size_t o = 0;
+            for (const auto& r : res) {
+                HIPCHK(launch_diff(r.first, static_cast<const char*>(ref.p) + o, r.second,
+                                   static_cast<unsigned long long*>(cnt.p), ops.st));
+                o += r.second;
+            }
             HIPCHK(hipMemcpyAsync(&bad, cnt.p, 8, hipMemcpyDeviceToHost, ops.st));
             HIPCHK(hipStreamSynchronize(ops.st));
             if (bad) {
@@ -503,14 +516,16 @@ struct Evaluator {
 // 11 bits, every value naming a configuration (codes that do not apply to a
 // mode are ignored, unusable ones fold onto usable ones):
 //   bit 0      kernel: 0 direct, 1 march; with bit 10: 0 flat, 1 march with
-//              two iterations per pass (batches: 0 flat, 1 march)
+//              two iterations per pass (batches: 0 flat, 1 march, with bit
+//              10 two iterations per pass)
 //   bits 1-2   bj: 1, 2, 4, 8 (direct: 1 reads as 2; two-iteration: 14, 6, 4, 8)
 //   bits 3-4   vec (march, one iteration): FP64 1, 2, 1, 2; FP32 1, 2, 4, 4;
 //              bit 3 is reread for two-iteration passes
 //   bits 5-7   one of 8 i-chunk lengths (march kernels)
 //   bit 8      non-temporal streams
-//   bit 9      XCD renumbering (single solve) / persistent grid (batch)
-//   bit 10     see bit 0 (single solves)
+//   bit 9      XCD renumbering (single solves, two-iteration batches) /
+//              persistent grid (one-iteration batches)
+//   bit 10     see bit 0
 // A flat kernel that does not fit the grid reads as the march kernel.
 constexpr int kGeneBits = 11;
 
@@ -534,13 +549,14 @@ bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_c
     const int b0 = g & 1, b10 = (g >> 10) & 1;
     if (batch) c.kernel = b0 ? HJ_KERNEL_MARCH : HJ_KERNEL_FLAT;
     else c.kernel = b0 ? HJ_KERNEL_MARCH : (b10 ? HJ_KERNEL_FLAT : HJ_KERNEL_DIRECT);
-    c.tsteps = (!batch && b0 && b10) ? 2 : 1;
+    c.tsteps = (b0 && b10) ? 2 : 1;
     const int bi = (g >> 1) & 3, vi = (g >> 3) & 3, sel = (g >> 5) & 7;
     c.bj = kBj[bi];
     c.vec = dtype == HJ_F64 ? kVec64[vi] : kVec32[vi];
     c.nontemporal = (g >> 8) & 1;
-    c.xcd_remap = batch ? 0 : (int)((g >> 9) & 1);
-    c.persistent = batch ? (int)((g >> 9) & 1) : 0;
+    const bool b9 = (g >> 9) & 1;
+    c.xcd_remap = (!batch || c.tsteps == 2) ? b9 : 0;
+    c.persistent = (batch && c.tsteps == 1) ? b9 : 0;
     if (c.kernel == HJ_KERNEL_FLAT) {
         if (c.bj == 1) c.bj = 2;
         c.vec = 1;
@@ -557,7 +573,7 @@ bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_c
         c.bj = kBjFused[bi];
         c.vec = 1;
         c.reread = vi & 1;
-        c.ichunk = gene_ichunk(sel, c, nx, ny, nz);
+        c.ichunk = batch ? (4 << sel) : gene_ichunk(sel, c, nx, ny, nz);
     } else {
         c.ichunk = batch ? (1 << sel) : gene_ichunk(sel, c, nx, ny, nz);
     }
@@ -872,7 +888,6 @@ int validate_config(int dtype, const hj_config* c)
     return HJ_OK;
 }
 
-// Candidate configurations of the autotuner for one grid.
 // The autotuner's candidates for one grid; cus is the device's CU count
 // (two-iteration chunks are sized to whole waves of resident workgroups).
 std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch, int cus)
@@ -1205,7 +1220,8 @@ struct SolverTuning {
         ev.ops.restore = [this] { restore(); };
         ev.ops.run = [this](int n) { h->run(n, 0.8, static_cast<double*>(h->gosa.p)); };
         ev.ops.result = [this] {
-            return std::make_pair((const void*)h->field(h->parity ? HJ_WRK2 : HJ_P), h->L.field_bytes);
+            return std::vector<std::pair<const void*, size_t>>{
+                {(const void*)h->field(h->parity ? HJ_WRK2 : HJ_P), h->L.field_bytes}};
         };
     }
     void restore()
@@ -1387,6 +1403,36 @@ int hj_copy_probe(void* dst, const void* src, unsigned long long bytes, void* st
 // batch of independent solves
 // ============================================================================
 
+namespace {
+
+// Default batch configuration: the march kernel, one iteration per pass.
+hj_config batch_default(int dtype)
+{
+    hj_config c = default_config(dtype);
+    c.kernel = HJ_KERNEL_MARCH;
+    c.bj = 4;
+    c.vec = 1;
+    c.ichunk = 16;
+    c.xcd_remap = 0;
+    c.persistent = 0;
+    return c;
+}
+
+}  // namespace
+
+// The flattened tile list of every instance of a batch for one configuration.
+struct BatchTiles {
+    DevBuf d_inst, d_tile_inst, d_seg;
+    int ntiles = 0, grid = 0;
+
+    void release()
+    {
+        d_inst.release();
+        d_tile_inst.release();
+        d_seg.release();
+    }
+};
+
 struct hj_batch_s {
     uint64_t magic = kBatchMagic;
     int dtype = HJ_F32;
@@ -1402,9 +1448,9 @@ struct hj_batch_s {
     std::vector<unsigned> uploaded;
     hj_config cfg;
     int cus = 256;
-    // tile list of the current configuration
-    DevBuf d_inst, d_tile_inst, d_seg;
-    int ntiles = 0, grid = 0;
+    // tile lists of the current configuration and, for two-iteration passes,
+    // of the one-iteration configuration that runs an odd remainder and the residual
+    BatchTiles tl, tl1;
     hj_config tiled_for;
     bool tiled = false;
     DevBuf part, gosa;
@@ -1415,8 +1461,19 @@ struct hj_batch_s {
     char* field(int inst, int q) const { return slab + off[inst] + (size_t)q * L[inst].field_stride; }
     char* origin(int inst, int q) const { return field(inst, q) + (size_t)(L[inst].A - 1) * L[inst].esz; }
 
+    bool two() const { return fused_of(cfg); }
+    hj_config single_cfg() const
+    {
+        if (!two()) return cfg;
+        hj_config c = batch_default(dtype);
+        c.nontemporal = 1;
+        c.use_graph = cfg.use_graph;
+        return c;
+    }
+    const BatchTiles& single_tiles() const { return two() ? tl1 : tl; }
+
     template <typename T>
-    void build_tiles_t()
+    void build_tiles_t(const hj_config& c, BatchTiles& out)
     {
         std::vector<Instance<T>> inst(n);
         std::vector<int> tile_inst;
@@ -1428,10 +1485,10 @@ struct hj_batch_s {
             d.f[1] = reinterpret_cast<T*>(origin(t, HJ_WRK2));
             for (int q = 0; q < NCOEF; ++q) d.coef[q] = reinterpret_cast<const T*>(origin(t, HJ_A0 + q));
             d.nx = l.nx; d.ny = l.ny; d.nz = l.nz; d.P = l.P; d.S = l.S;
-            const TileCounts tc = tile_counts(cfg, l.nx, l.ny, l.nz);
+            const TileCounts tc = tile_counts(c, l.nx, l.ny, l.nz);
             d.kt_n = tc.kt_n;
             d.jt_n = tc.jt_n;
-            d.ichunk = cfg.ichunk;
+            d.ichunk = c.ichunk;
             d.tile0 = (int)tile_inst.size();
             seg[t] = d.tile0;
             const long long nt = tc.tiles();
@@ -1439,19 +1496,25 @@ struct hj_batch_s {
             tile_inst.insert(tile_inst.end(), (size_t)nt, t);
         }
         seg[n] = (int)tile_inst.size();
-        ntiles = (int)tile_inst.size();
-        d_inst.ensure(sizeof(Instance<T>) * std::max(n, 1));
-        d_tile_inst.ensure(sizeof(int) * std::max(ntiles, 1));
-        d_seg.ensure(sizeof(int) * (n + 1));
-        HIPCHK(hipMemcpy(d_inst.p, inst.data(), sizeof(Instance<T>) * n, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(d_tile_inst.p, tile_inst.data(), sizeof(int) * ntiles, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(d_seg.p, seg.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
-        if (cfg.persistent) {
-            const int occ = batch_occupancy<T>(cfg);
-            grid = std::max(1, std::min(ntiles, std::max(occ, 1) * cus));
+        out.ntiles = (int)tile_inst.size();
+        out.d_inst.ensure(sizeof(Instance<T>) * std::max(n, 1));
+        out.d_tile_inst.ensure(sizeof(int) * std::max(out.ntiles, 1));
+        out.d_seg.ensure(sizeof(int) * (n + 1));
+        HIPCHK(hipMemcpy(out.d_inst.p, inst.data(), sizeof(Instance<T>) * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(out.d_tile_inst.p, tile_inst.data(), sizeof(int) * out.ntiles, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(out.d_seg.p, seg.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+        if (c.persistent) {
+            const int occ = batch_occupancy<T>(c);
+            out.grid = std::max(1, std::min(out.ntiles, std::max(occ, 1) * cus));
         } else {
-            grid = ntiles;
+            out.grid = out.ntiles;
         }
+    }
+
+    void build_list(const hj_config& c, BatchTiles& out)
+    {
+        if (dtype == HJ_F64) build_tiles_t<double>(c, out);
+        else build_tiles_t<float>(c, out);
     }
 
     void build_tiles()
@@ -1461,44 +1524,86 @@ struct hj_batch_s {
             if (!config_fits(dtype, cfg, l.nx, l.ny, l.nz))
                 throw HipFail{hipErrorInvalidValue, "configuration does not fit an instance", __LINE__};
         graphs.clear();
-        if (dtype == HJ_F64) build_tiles_t<double>();
-        else build_tiles_t<float>();
+        tiled = false;
+        build_list(cfg, tl);
+        if (two()) build_list(single_cfg(), tl1);
         tiled_for = cfg;
         tiled = true;
     }
 
-    hipError_t launch_one(int par, double omega, bool write, double* part_out, hipStream_t st) const
+    // Partials per iteration slot (room for either list's tiles).
+    long long stride() const { return two() ? std::max(tl.ntiles, tl1.ntiles) : tl.ntiles; }
+    // Iterations per block of partials; pairs of a two-iteration pass never straddle two blocks.
+    int chunk_of(int n_iter) const
+    {
+        int ch = chunk_iters(std::max(n_iter, 1), stride());
+        if (two()) ch = std::max(2, ch & ~1);
+        return ch;
+    }
+    int launches(int n_iter) const { return two() ? n_iter / 2 + (n_iter & 1) : n_iter; }
+
+    hipError_t launch_one(const hj_config& c, const BatchTiles& t, int par, double omega, bool write,
+                          double* part_out, hipStream_t st) const
     {
         if (dtype == HJ_F64)
-            return launch_batch<double>(cfg, static_cast<const Instance<double>*>(d_inst.p),
-                                        static_cast<const int*>(d_tile_inst.p), ntiles, grid, par, omega,
+            return launch_batch<double>(c, static_cast<const Instance<double>*>(t.d_inst.p),
+                                        static_cast<const int*>(t.d_tile_inst.p), t.ntiles, t.grid, par, omega,
                                         write, part_out, st);
-        return launch_batch<float>(cfg, static_cast<const Instance<float>*>(d_inst.p),
-                                   static_cast<const int*>(d_tile_inst.p), ntiles, grid, par, (float)omega,
+        return launch_batch<float>(c, static_cast<const Instance<float>*>(t.d_inst.p),
+                                   static_cast<const int*>(t.d_tile_inst.p), t.ntiles, t.grid, par, (float)omega,
                                    write, part_out, st);
     }
-
-    void enqueue(int n_iter, double omega, int par, double* out, hipStream_t st) const
+    hipError_t launch_two(int par, double omega, double* p1, double* p2, hipStream_t st) const
     {
-        const int ch = chunk_iters(n_iter, ntiles);
+        if (dtype == HJ_F64)
+            return launch_batch_fused<double>(cfg, static_cast<const Instance<double>*>(tl.d_inst.p),
+                                              static_cast<const int*>(tl.d_tile_inst.p), tl.ntiles, par, omega,
+                                              p1, p2, st);
+        return launch_batch_fused<float>(cfg, static_cast<const Instance<float>*>(tl.d_inst.p),
+                                         static_cast<const int*>(tl.d_tile_inst.p), tl.ntiles, par, (float)omega,
+                                         p1, p2, st);
+    }
+    hipError_t finalize(const double* pt, const BatchTiles& t, int slots, double* out, hipStream_t st) const
+    {
+        return launch_finalize(pt, stride(), t.ntiles, static_cast<const int*>(t.d_seg.p), n, slots, out, st);
+    }
+
+    // Enqueue n_iter iterations from parity `par`, gosa history [n_iter][n]
+    // to out. Returns the parity after them (one flip per launch).
+    int enqueue(int n_iter, double omega, int par, double* out, hipStream_t st) const
+    {
+        const long long sd = stride();
+        const int ch = chunk_of(n_iter);
+        const hj_config one = single_cfg();
+        const BatchTiles& t1 = single_tiles();
         double* pt = static_cast<double*>(part.p);
-        int it0 = 0;
-        for (int it = 0; it < n_iter; ++it) {
-            const int slot = it - it0;
-            HIPCHK(launch_one(par, omega, true, pt + (long long)slot * ntiles, st));
-            par ^= 1;
-            if (slot + 1 == ch || it == n_iter - 1) {
-                HIPCHK(launch_finalize(pt, ntiles, ntiles, static_cast<const int*>(d_seg.p), n, slot + 1,
-                                       out + (long long)it0 * n, st));
-                it0 = it + 1;
+        for (int it0 = 0; it0 < n_iter;) {
+            const int n_here = std::min(ch, n_iter - it0);
+            int slot = 0;
+            if (two()) {
+                for (; slot + 1 < n_here; slot += 2) {
+                    HIPCHK(launch_two(par, omega, pt + slot * sd, pt + (slot + 1) * sd, st));
+                    par ^= 1;
+                }
+                if (slot > 0) HIPCHK(finalize(pt, tl, slot, out + (long long)it0 * n, st));
             }
+            if (slot < n_here) {
+                const int first = slot;
+                for (; slot < n_here; ++slot) {
+                    HIPCHK(launch_one(one, t1, par, omega, true, pt + slot * sd, st));
+                    par ^= 1;
+                }
+                HIPCHK(finalize(pt + first * sd, t1, slot - first, out + (long long)(it0 + first) * n, st));
+            }
+            it0 += n_here;
         }
+        return par;
     }
 
     void reserve(int n_iter)
     {
         build_tiles();
-        const size_t need_part = (size_t)chunk_iters(std::max(n_iter, 1), ntiles) * (size_t)std::max(ntiles, 1) * 8;
+        const size_t need_part = (size_t)chunk_of(n_iter) * (size_t)std::max<long long>(stride(), 1) * 8;
         const size_t need_gosa = (size_t)std::max(n_iter, 1) * (size_t)n * 8;
         if (need_part > part.bytes || need_gosa > gosa.bytes) {
             graphs.clear();
@@ -1517,10 +1622,10 @@ struct hj_batch_s {
                 graphs.add(GraphEntry{n_iter, bits_of(omega), parity, cfg, out, ex});
             }
             HIPCHK(hipGraphLaunch(ex, stream));
+            parity ^= (launches(n_iter) & 1);
         } else {
-            enqueue(n_iter, omega, parity, out, stream);
+            parity = enqueue(n_iter, omega, parity, out, stream);
         }
-        parity ^= (n_iter & 1);
     }
 
     bool all_uploaded() const
@@ -1547,15 +1652,15 @@ int check_batch(hj_batch b)
     return HJ_OK;
 }
 
-hj_config batch_default(int dtype)
+// The form a batch runs a configuration in: XCD renumbering and reread
+// apply to two-iteration passes only.
+hj_config batch_form(hj_config c)
 {
-    hj_config c = default_config(dtype);
-    c.kernel = HJ_KERNEL_MARCH;
-    c.bj = 4;
-    c.vec = 1;
-    c.ichunk = 16;
-    c.xcd_remap = 0;
-    c.persistent = 0;
+    if (c.tsteps == 0) c.tsteps = 1;
+    if (c.tsteps != 2) {
+        c.xcd_remap = 0;
+        c.reread = 0;
+    }
     return c;
 }
 
@@ -1591,10 +1696,9 @@ int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* n
         {
             hj_config c;
             if (cache_get("batch", dtype, batch_key(b->L), c) && config_supported(dtype, c) &&
-                c.kernel != HJ_KERNEL_DIRECT && c.tsteps != 2 && batch_fits(b, c)) {
+                c.kernel != HJ_KERNEL_DIRECT && batch_fits(b, c)) {
                 c.use_graph = 1;
-                c.xcd_remap = 0;
-                b->cfg = c;
+                b->cfg = batch_form(c);
             }
         }
         try {
@@ -1710,9 +1814,9 @@ int hj_batch_residual(hj_batch b, double* gosa)
         b->reserve(1);
         double* pt = static_cast<double*>(b->part.p);
         double* out = static_cast<double*>(b->gosa.p);
-        HIPCHK(b->launch_one(b->parity, 0.0, false, pt, b->stream));
-        HIPCHK(launch_finalize(pt, b->ntiles, b->ntiles, static_cast<const int*>(b->d_seg.p), b->n, 1, out,
-                               b->stream));
+        const BatchTiles& t = b->single_tiles();
+        HIPCHK(b->launch_one(b->single_cfg(), t, b->parity, 0.0, false, pt, b->stream));
+        HIPCHK(b->finalize(pt, t, 1, out, b->stream));
         b->host_gosa.ensure((size_t)b->n * 8);
         HIPCHK(hipMemcpyAsync(b->host_gosa.p, out, (size_t)b->n * 8, hipMemcpyDeviceToHost, b->stream));
         HIPCHK(hipStreamSynchronize(b->stream));
@@ -1734,14 +1838,10 @@ int hj_batch_set_config(hj_batch b, const hj_config* cfg)
     if (int rc = check_batch(b)) return rc;
     if (int rc = validate_config(b->dtype, cfg)) return rc;
     if (cfg->kernel == HJ_KERNEL_DIRECT) return set_err(HJ_ERR_ARG, "batches run the march or flat kernel");
-    if (cfg->tsteps == 2) return set_err(HJ_ERR_ARG, "batches run one iteration per pass");
     if (!batch_fits(b, *cfg)) return set_err(HJ_ERR_ARG, "the flat kernel does not fit every instance");
     return guarded([&]() -> int {
         b->graphs.clear();
-        b->cfg = *cfg;
-        b->cfg.xcd_remap = 0;
-        b->cfg.tsteps = 1;
-        b->cfg.reread = 0;
+        b->cfg = batch_form(*cfg);
         return HJ_OK;
     });
 }
@@ -1772,13 +1872,20 @@ struct BatchTuning {
         ev.ops.e1 = b->ev1;
         ev.ops.set = [this](const hj_config& c) {
             if (!batch_fits(b, c)) throw HipFail{hipErrorInvalidValue, "flat kernel does not fit", __LINE__};
-            b->cfg = c;
+            b->cfg = batch_form(c);
             b->cfg.use_graph = 1;
             b->reserve(ev.n_sweeps);
         };
         ev.ops.restore = [this] { restore(); };
         ev.ops.run = [this](int n) { b->run(n, 0.8, static_cast<double*>(b->gosa.p)); };
-        ev.ops.result = [this] { return std::make_pair((const void*)b->slab, b->slab_bytes); };
+        ev.ops.result = [this] {
+            // the current p of every instance (the partner buffer holds an
+            // earlier iterate, which differs between one- and two-iteration passes)
+            std::vector<std::pair<const void*, size_t>> r;
+            for (int t = 0; t < b->n; ++t)
+                r.emplace_back((const void*)b->field(t, b->parity ? HJ_WRK2 : HJ_P), b->L[t].field_bytes);
+            return r;
+        };
     }
     void restore()
     {
@@ -1835,6 +1942,16 @@ std::vector<hj_config> batch_candidates(const hj_batch_s* b)
                         c.bj = bj; c.vec = v; c.ichunk = ich; c.nontemporal = nt; c.persistent = per;
                         if (config_supported(dtype, c)) out.push_back(c);
                     }
+    // two iterations per pass, one workgroup per tile, with and without XCD renumbering
+    for (int bj : {6, 8, 14})
+        for (int ich : {8, 12, 16, 24, 32, 48, 64, 128})
+            for (int rr : {0, 1})
+                for (int rm : {0, 1}) {
+                    hj_config c = batch_default(dtype);
+                    c.bj = bj; c.vec = 1; c.ichunk = ich; c.nontemporal = 0; c.tsteps = 2; c.reread = rr;
+                    c.xcd_remap = rm;
+                    if (config_supported(dtype, c)) out.push_back(c);
+                }
     return out;
 }
 
@@ -1933,9 +2050,8 @@ int hj_batch_destroy(hj_batch b)
     b->part.release();
     b->gosa.release();
     b->host_gosa.release();
-    b->d_inst.release();
-    b->d_tile_inst.release();
-    b->d_seg.release();
+    b->tl.release();
+    b->tl1.release();
     (void)hipFree(b->slab);
     if (b->owns_stream) (void)hipStreamDestroy(b->stream);
     (void)hipStreamDestroy(b->cap);

@@ -261,6 +261,29 @@ hipError_t fused_go(const hj_config& c, const Grid<T>& g, T omega, double* part1
     return hipGetLastError();
 }
 
+template <typename T, int BJ, bool NT, bool KEEP>
+hipError_t fused_batch_go(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
+                          int parity, T omega, double* part1, double* part2, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fused_batch_kernel<T, BJ, NT, KEEP>), dim3((unsigned)ntiles), dim3(kWave * (BJ + 2)), 0,
+                       st, inst, tile_inst, parity, omega, c.xcd_remap, part1, part2);
+    return hipGetLastError();
+}
+
+template <typename T, int BJ>
+hipError_t fused_batch_bj(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
+                          int parity, T omega, double* part1, double* part2, hipStream_t st)
+{
+    if (c.reread)
+        return c.nontemporal
+                   ? fused_batch_go<T, BJ, true, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
+                   : fused_batch_go<T, BJ, false, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+    return c.nontemporal
+               ? fused_batch_go<T, BJ, true, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
+               : fused_batch_go<T, BJ, false, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+}
+
 template <typename T, int BJ>
 hipError_t fused_bj(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                     hipStream_t st)
@@ -323,6 +346,27 @@ hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* p
     default: return hipErrorInvalidValue;
     }
 }
+
+template <typename T>
+hipError_t launch_batch_fused(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
+                              int parity, T omega, double* part1, double* part2, hipStream_t st)
+{
+    if (!fused_of(c) || c.kernel != HJ_KERNEL_MARCH || c.vec != 1 || c.ichunk < 1 || c.persistent)
+        return hipErrorInvalidValue;
+    switch (c.bj) {
+    case 2: return fused_batch_bj<T, 2>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+    case 4: return fused_batch_bj<T, 4>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+    case 6: return fused_batch_bj<T, 6>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+    case 8: return fused_batch_bj<T, 8>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+    case 14: return fused_batch_bj<T, 14>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_batch_fused<double>(const hj_config&, const Instance<double>*, const int*, int, int,
+                                               double, double*, double*, hipStream_t);
+template hipError_t launch_batch_fused<float>(const hj_config&, const Instance<float>*, const int*, int, int,
+                                              float, double*, double*, hipStream_t);
 
 template hipError_t launch_fused<double>(const hj_config&, const Grid<double>&, double, double*, double*,
                                          hipStream_t);

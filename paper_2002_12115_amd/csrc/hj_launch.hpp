@@ -73,6 +73,13 @@ template <typename T>
 hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                         hipStream_t st);
 
+// Two iterations over every instance of a batch (tsteps 2, not persistent):
+// one workgroup per tile of the flattened list, built with the two-iteration
+// tile counts; per-tile partials of the two iterations to part1 and part2.
+template <typename T>
+hipError_t launch_batch_fused(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
+                              int parity, T omega, double* part1, double* part2, hipStream_t st);
+
 // Workgroups of the two-iteration kernel named by c resident per CU (0 when
 // c names none, or the query fails).
 template <typename T>

@@ -560,18 +560,13 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
     }
 }
 
+// One workgroup's whole share of a two-iteration pass: tile (kt, jt), i-chunk
+// ic, both iterations' gosa partials to slot L of part1 / part2.
 template <typename T, int BJ, bool NT, bool KEEP>
-__global__ __launch_bounds__(kWave * (BJ + 2)) __attribute__((amdgpu_waves_per_eu(BJ == 6 ? 4 : 1))) void fused_kernel(Grid<T> g, T omega, int ichunk, int kt_n,
-                                                                  int jt_n, int remap,
-                                                                  double* __restrict__ part1,
-                                                                  double* __restrict__ part2)
+__device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, int jt, int ic, int ichunk, int L,
+                                            FusedLds<T, BJ>& sm, double* __restrict__ part1,
+                                            double* __restrict__ part2)
 {
-    __shared__ FusedLds<T, BJ> sm;
-    const int nb = gridDim.x;
-    const int L = remap_xcd(blockIdx.x, nb, remap);
-    const int kt = L % kt_n;
-    const int jt = (L / kt_n) % jt_n;
-    const int ic = L / (kt_n * jt_n);
     const int ib = 1 + ic * ichunk;
     int ie = ib + ichunk;
     if (ie > g.nx - 1) ie = g.nx - 1;
@@ -581,6 +576,45 @@ __global__ __launch_bounds__(kWave * (BJ + 2)) __attribute__((amdgpu_waves_per_e
     if (threadIdx.x == 0) part1[L] = acc1;
     acc2 = block_sum<BJ + 2>(acc2, sm.red);
     if (threadIdx.x == 0) part2[L] = acc2;
+}
+
+// bj 6 asks for four waves per SIMD, so that two of its 8-wave workgroups
+// share a CU (it then holds 128 VGPRs and spills a few).
+template <typename T, int BJ, bool NT, bool KEEP>
+__global__ __launch_bounds__(kWave * (BJ + 2)) __attribute__((amdgpu_waves_per_eu(BJ == 6 ? 4 : 1))) void fused_kernel(
+    Grid<T> g, T omega, int ichunk, int kt_n, int jt_n, int remap, double* __restrict__ part1,
+    double* __restrict__ part2)
+{
+    __shared__ FusedLds<T, BJ> sm;
+    const int L = remap_xcd(blockIdx.x, gridDim.x, remap);
+    const int kt = L % kt_n;
+    const int jt = (L / kt_n) % jt_n;
+    const int ic = L / (kt_n * jt_n);
+    fused_block<T, BJ, NT, KEEP>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
+}
+
+// Two iterations over every instance of a batch: one workgroup per tile of
+// the flattened list (instance descriptors as for batch_kernel, with the
+// two-iteration tile counts), gridDim.x == the number of tiles.
+template <typename T, int BJ, bool NT, bool KEEP>
+__global__ __launch_bounds__(kWave * (BJ + 2)) __attribute__((amdgpu_waves_per_eu(BJ == 6 ? 4 : 1))) void fused_batch_kernel(
+    const Instance<T>* __restrict__ inst, const int* __restrict__ tile_inst, int parity, T omega, int remap,
+    double* __restrict__ part1, double* __restrict__ part2)
+{
+    __shared__ FusedLds<T, BJ> sm;
+    const int L = remap_xcd(blockIdx.x, gridDim.x, remap);
+    const Instance<T>& d = inst[tile_inst[L]];
+    Grid<T> g;
+#pragma unroll
+    for (int q = 0; q < NCOEF; ++q) g.coef[q] = d.coef[q];
+    g.src = d.f[parity];
+    g.dst = d.f[parity ^ 1];
+    g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.P = d.P; g.S = d.S;
+    const int t = L - d.tile0;
+    const int kt = t % d.kt_n;
+    const int jt = (t / d.kt_n) % d.jt_n;
+    const int ic = t / (d.kt_n * d.jt_n);
+    fused_block<T, BJ, NT, KEEP>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
 }
 
 // ---- flat kernel: tiles of consecutive interior (j,k) cells -------------------

@@ -171,7 +171,12 @@ def test_gene_decoding(lib):
             for g in range(2 ** 11):
                 d = dec(dtype, g, batch)
                 if batch:
-                    assert d["kernel"] in (1, 2) and d["tsteps"] == 1 and d["xcd_remap"] == 0
+                    assert d["kernel"] in (1, 2)
+                    if d["tsteps"] == 2:                # two-iteration batches: renumbering, no persistent grid
+                        assert d["kernel"] == 1 and d["persistent"] == 0 and d["ichunk"] == 4 << ((g >> 5) & 7)
+                        assert d["xcd_remap"] == (g >> 9) & 1
+                    else:
+                        assert d["tsteps"] == 1 and d["xcd_remap"] == 0
     # folded codes: vec code 2 is 1 for FP64 and 4 for FP32; direct reads bj 1 as 2
     assert dec(0, 1 | (2 << 3))["vec"] == 1 and dec(1, 1 | (2 << 3))["vec"] == 4
     assert dec(0, 0)["bj"] == 2 and dec(0, 0)["kernel"] == 0
