@@ -76,12 +76,14 @@ enum hj_field {
  * xcd_remap: renumber workgroups so neighbouring tiles share an XCD's L2.
  * persistent (batches only): launch as many workgroups as stay resident and
  * let each loop over tiles, instead of one workgroup per tile.
- * tsteps: Jacobi iterations per pass over memory (single solves). 1, or 2:
- * the march kernel computes the first iteration of a tile and its one-cell
- * halo into LDS and the second from it, so each coefficient is read once
- * per two iterations (needs kernel HJ_KERNEL_MARCH, vec 1, bj 2, 4, 6, 8 or 14;
- * an odd remainder runs one single-iteration launch). 0 means 1. The
- * results are bitwise those of tsteps 1.
+ * tsteps: Jacobi iterations per pass over memory. 1, or 2: the march
+ * kernel computes the first iteration of a tile and its one-cell halo into
+ * LDS and the second from it, so each coefficient is read once per two
+ * iterations. Needs kernel HJ_KERNEL_MARCH, not persistent, and vec 1
+ * (tiles of 62-cell rows, each a 64-lane row with its halo; bj 2, 4, 6, 8
+ * or 14) or vec 2 (tiles of 64-cell rows, one more wave computing the halo
+ * columns; bj 2, 4, 6, 8 or 12). An odd remainder runs one single-iteration
+ * launch. 0 means 1. The results are bitwise those of tsteps 1.
  * reread (tsteps 2 only): 0 holds each cell's coefficients in registers
  * between its two iterations, 1 reads them again for the second (an L2 hit
  * when nontemporal is 0), which frees registers for more resident waves. */
@@ -181,7 +183,8 @@ int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long l
  * with two iterations per pass (1). bits 1-2: bj 1, 2, 4, 8 (the direct
  * kernel reads 1 as 2; two-iteration passes read the codes as 14, 6, 4, 8).
  * bits 3-4: vec 1, 2, 1, 2 (FP64) or 1, 2, 4, 4 (FP32) for the
- * one-iteration march kernel; bit 3 is reread for two-iteration passes.
+ * one-iteration march kernel; for two-iteration passes bit 3 is reread and
+ * bit 4 selects vec 2 (where bj 14 reads as 12).
  * bits 5-7: the i-chunk n, giving about 512 << n workgroups; for
  * two-iteration passes the longest chunk within 256, 512, 768, 1024, 2048,
  * 4096, 8192 or 24576 workgroups; for batches 2^n planes (one-iteration)

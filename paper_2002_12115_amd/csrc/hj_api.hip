@@ -520,7 +520,8 @@ struct Evaluator {
 //              10 two iterations per pass)
 //   bits 1-2   bj: 1, 2, 4, 8 (direct: 1 reads as 2; two-iteration: 14, 6, 4, 8)
 //   bits 3-4   vec (march, one iteration): FP64 1, 2, 1, 2; FP32 1, 2, 4, 4;
-//              bit 3 is reread for two-iteration passes
+//              two-iteration passes: bit 3 is reread, bit 4 the 64-cell rows
+//              with a halo wave (vec 2, where bj 14 reads as 12)
 //   bits 5-7   one of 8 i-chunk lengths (march kernels)
 //   bit 8      non-temporal streams
 //   bit 9      XCD renumbering (single solves, two-iteration batches) /
@@ -571,7 +572,8 @@ bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_c
         c.ichunk = 1;
     } else if (c.tsteps == 2) {
         c.bj = kBjFused[bi];
-        c.vec = 1;
+        c.vec = (vi >> 1) ? 2 : 1;
+        if (c.vec == 2 && c.bj == 14) c.bj = 12;
         c.reread = vi & 1;
         c.ichunk = batch ? (4 << sel) : gene_ichunk(sel, c, nx, ny, nz);
     } else {
@@ -950,16 +952,18 @@ std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch,
                     for (const hj_config& y : out) dup = dup || same_config(x, y);
                     if (!dup && config_fits(dtype, x, nx, ny, nz)) out.push_back(x);
                 }
-        // two iterations per pass: long chunks (the halo planes of a chunk are
-        // recomputed), sized to 1 .. 64 waves of resident workgroups; XCD
-        // renumbering lets neighbouring tiles share their halo reads in L2
-        for (int bj : {6, 8, 14})
+        // two iterations per pass (62-cell rows, or 64-cell rows with a halo
+        // wave): long chunks (the halo planes of a chunk are recomputed), sized
+        // to 1 .. 64 waves of resident workgroups; XCD renumbering lets
+        // neighbouring tiles share their halo reads in L2
+        static const std::pair<int, int> kFusedShapes[] = {{1, 6}, {1, 8}, {1, 14}, {2, 4}, {2, 6}, {2, 8}, {2, 12}};
+        for (const auto& vb : kFusedShapes)
             for (int rr : {0, 1})
-                for (int rm : {0, 1}) {
+                for (int rm : {1}) {
                     hj_config x = base;
                     x.kernel = HJ_KERNEL_MARCH;
-                    x.bj = bj;
-                    x.vec = 1;
+                    x.bj = vb.second;
+                    x.vec = vb.first;
                     x.tsteps = 2;
                     x.reread = rr;
                     x.nontemporal = 0;
@@ -1942,16 +1946,16 @@ std::vector<hj_config> batch_candidates(const hj_batch_s* b)
                         c.bj = bj; c.vec = v; c.ichunk = ich; c.nontemporal = nt; c.persistent = per;
                         if (config_supported(dtype, c)) out.push_back(c);
                     }
-    // two iterations per pass, one workgroup per tile, with and without XCD renumbering
-    for (int bj : {6, 8, 14})
+    // two iterations per pass, one workgroup per tile, XCD renumbering
+    static const std::pair<int, int> kFusedShapes[] = {{1, 6}, {1, 8}, {1, 14}, {2, 4}, {2, 6}, {2, 8}, {2, 12}};
+    for (const auto& vb : kFusedShapes)
         for (int ich : {8, 12, 16, 24, 32, 48, 64, 128})
-            for (int rr : {0, 1})
-                for (int rm : {0, 1}) {
-                    hj_config c = batch_default(dtype);
-                    c.bj = bj; c.vec = 1; c.ichunk = ich; c.nontemporal = 0; c.tsteps = 2; c.reread = rr;
-                    c.xcd_remap = rm;
-                    if (config_supported(dtype, c)) out.push_back(c);
-                }
+            for (int rr : {0, 1}) {
+                hj_config c = batch_default(dtype);
+                c.bj = vb.second; c.vec = vb.first; c.ichunk = ich; c.nontemporal = 0; c.tsteps = 2;
+                c.reread = rr; c.xcd_remap = 1;
+                if (config_supported(dtype, c)) out.push_back(c);
+            }
     return out;
 }
 

@@ -117,9 +117,12 @@ bool config_supported(int dtype, const hj_config& c)
     if (dtype != HJ_F64 && dtype != HJ_F32) return false;
     if (c.tsteps < 0 || c.tsteps > 2 || c.reread < 0 || c.reread > 1) return false;
     if (c.xcd_remap < 0 || c.xcd_remap > 1) return false;
-    if (c.tsteps == 2)
-        return c.kernel == HJ_KERNEL_MARCH && c.vec == 1 && c.ichunk >= 1 && c.persistent == 0 &&
-               (c.bj == 2 || c.bj == 4 || c.bj == 6 || c.bj == 8 || c.bj == 14);
+    if (c.tsteps == 2) {
+        if (c.kernel != HJ_KERNEL_MARCH || c.ichunk < 1 || c.persistent != 0) return false;
+        if (c.vec == 1) return c.bj == 2 || c.bj == 4 || c.bj == 6 || c.bj == 8 || c.bj == 14;
+        if (c.vec == 2) return c.bj == 2 || c.bj == 4 || c.bj == 6 || c.bj == 8 || c.bj == 12;
+        return false;
+    }
     if (c.kernel == HJ_KERNEL_FLAT) return (c.bj == 2 || c.bj == 4 || c.bj == 8) && c.vec == 1 && c.ichunk >= 1;
     if (!bj_ok(c.bj)) return false;
     if (c.kernel == HJ_KERNEL_DIRECT) return c.bj >= 2;
@@ -271,29 +274,85 @@ hipError_t fused_batch_go(const hj_config& c, const Instance<T>* inst, const int
     return hipGetLastError();
 }
 
+template <typename T, int BJ, bool NT, bool KEEP>
+hipError_t wide_go(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2, hipStream_t st)
+{
+    const TileCounts t = tile_counts(c, g.nx, g.ny, g.nz);
+    const long long nb = t.tiles();
+    if (nb <= 0) return hipSuccess;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((wide_kernel<T, BJ, NT, KEEP>), dim3((unsigned)nb), dim3(kWave * (BJ + 3)), 0, st, g, omega,
+                       c.ichunk, t.kt_n, t.jt_n, c.xcd_remap, part1, part2);
+    return hipGetLastError();
+}
+
+template <typename T, int BJ, bool NT, bool KEEP>
+hipError_t wide_batch_go(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
+                         int parity, T omega, double* part1, double* part2, hipStream_t st)
+{
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((wide_batch_kernel<T, BJ, NT, KEEP>), dim3((unsigned)ntiles), dim3(kWave * (BJ + 3)), 0,
+                       st, inst, tile_inst, parity, omega, c.xcd_remap, part1, part2);
+    return hipGetLastError();
+}
+
 template <typename T, int BJ>
 hipError_t fused_batch_bj(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
                           int parity, T omega, double* part1, double* part2, hipStream_t st)
 {
-    if (c.reread)
+    if (c.vec == 2) {
+        if constexpr (BJ + 3 <= 16) {
+            if (c.reread)
+                return c.nontemporal
+                           ? wide_batch_go<T, BJ, true, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
+                           : wide_batch_go<T, BJ, false, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2,
+                                                                st);
+            return c.nontemporal
+                       ? wide_batch_go<T, BJ, true, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
+                       : wide_batch_go<T, BJ, false, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+    if constexpr (BJ + 2 <= 16) {
+        if (c.reread)
+            return c.nontemporal
+                       ? fused_batch_go<T, BJ, true, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
+                       : fused_batch_go<T, BJ, false, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2,
+                                                             st);
         return c.nontemporal
-                   ? fused_batch_go<T, BJ, true, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
-                   : fused_batch_go<T, BJ, false, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
-    return c.nontemporal
-               ? fused_batch_go<T, BJ, true, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
-               : fused_batch_go<T, BJ, false, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+                   ? fused_batch_go<T, BJ, true, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
+                   : fused_batch_go<T, BJ, false, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int BJ>
 hipError_t fused_bj(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                     hipStream_t st)
 {
-    if (c.reread) {
-        return c.nontemporal ? fused_go<T, BJ, true, false>(c, g, omega, part1, part2, st)
-                             : fused_go<T, BJ, false, false>(c, g, omega, part1, part2, st);
+    if (c.vec == 2) {
+        if constexpr (BJ + 3 <= 16) {
+            if (c.reread)
+                return c.nontemporal ? wide_go<T, BJ, true, false>(c, g, omega, part1, part2, st)
+                                     : wide_go<T, BJ, false, false>(c, g, omega, part1, part2, st);
+            return c.nontemporal ? wide_go<T, BJ, true, true>(c, g, omega, part1, part2, st)
+                                 : wide_go<T, BJ, false, true>(c, g, omega, part1, part2, st);
+        } else {
+            return hipErrorInvalidValue;
+        }
     }
-    return c.nontemporal ? fused_go<T, BJ, true, true>(c, g, omega, part1, part2, st)
-                         : fused_go<T, BJ, false, true>(c, g, omega, part1, part2, st);
+    if constexpr (BJ + 2 <= 16) {
+        if (c.reread) {
+            return c.nontemporal ? fused_go<T, BJ, true, false>(c, g, omega, part1, part2, st)
+                                 : fused_go<T, BJ, false, false>(c, g, omega, part1, part2, st);
+        }
+        return c.nontemporal ? fused_go<T, BJ, true, true>(c, g, omega, part1, part2, st)
+                             : fused_go<T, BJ, false, true>(c, g, omega, part1, part2, st);
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int BJ, bool NT, bool KEEP>
@@ -306,11 +365,33 @@ int fused_occ()
     return n;
 }
 
+template <typename T, int BJ, bool NT, bool KEEP>
+int wide_occ()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wide_kernel<T, BJ, NT, KEEP>, kWave * (BJ + 3), 0) !=
+        hipSuccess)
+        return 0;
+    return n;
+}
+
 template <typename T, int BJ>
 int fused_occ_bj(const hj_config& c)
 {
-    if (c.reread) return c.nontemporal ? fused_occ<T, BJ, true, false>() : fused_occ<T, BJ, false, false>();
-    return c.nontemporal ? fused_occ<T, BJ, true, true>() : fused_occ<T, BJ, false, true>();
+    if (c.vec == 2) {
+        if constexpr (BJ + 3 <= 16) {
+            if (c.reread) return c.nontemporal ? wide_occ<T, BJ, true, false>() : wide_occ<T, BJ, false, false>();
+            return c.nontemporal ? wide_occ<T, BJ, true, true>() : wide_occ<T, BJ, false, true>();
+        } else {
+            return 0;
+        }
+    }
+    if constexpr (BJ + 2 <= 16) {
+        if (c.reread) return c.nontemporal ? fused_occ<T, BJ, true, false>() : fused_occ<T, BJ, false, false>();
+        return c.nontemporal ? fused_occ<T, BJ, true, true>() : fused_occ<T, BJ, false, true>();
+    } else {
+        return 0;
+    }
 }
 
 }  // namespace
@@ -324,6 +405,7 @@ int fused_occupancy(const hj_config& c)
     case 4: return fused_occ_bj<T, 4>(c);
     case 6: return fused_occ_bj<T, 6>(c);
     case 8: return fused_occ_bj<T, 8>(c);
+    case 12: return fused_occ_bj<T, 12>(c);
     case 14: return fused_occ_bj<T, 14>(c);
     default: return 0;
     }
@@ -336,12 +418,14 @@ template <typename T>
 hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                         hipStream_t st)
 {
-    if (!fused_of(c) || c.kernel != HJ_KERNEL_MARCH || c.vec != 1 || c.ichunk < 1) return hipErrorInvalidValue;
+    if (!fused_of(c) || c.kernel != HJ_KERNEL_MARCH || (c.vec != 1 && c.vec != 2) || c.ichunk < 1)
+        return hipErrorInvalidValue;
     switch (c.bj) {
     case 2: return fused_bj<T, 2>(c, g, omega, part1, part2, st);
     case 4: return fused_bj<T, 4>(c, g, omega, part1, part2, st);
     case 6: return fused_bj<T, 6>(c, g, omega, part1, part2, st);
     case 8: return fused_bj<T, 8>(c, g, omega, part1, part2, st);
+    case 12: return fused_bj<T, 12>(c, g, omega, part1, part2, st);
     case 14: return fused_bj<T, 14>(c, g, omega, part1, part2, st);
     default: return hipErrorInvalidValue;
     }
@@ -351,13 +435,14 @@ template <typename T>
 hipError_t launch_batch_fused(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
                               int parity, T omega, double* part1, double* part2, hipStream_t st)
 {
-    if (!fused_of(c) || c.kernel != HJ_KERNEL_MARCH || c.vec != 1 || c.ichunk < 1 || c.persistent)
+    if (!fused_of(c) || c.kernel != HJ_KERNEL_MARCH || (c.vec != 1 && c.vec != 2) || c.ichunk < 1 || c.persistent)
         return hipErrorInvalidValue;
     switch (c.bj) {
     case 2: return fused_batch_bj<T, 2>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
     case 4: return fused_batch_bj<T, 4>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
     case 6: return fused_batch_bj<T, 6>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
     case 8: return fused_batch_bj<T, 8>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+    case 12: return fused_batch_bj<T, 12>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
     case 14: return fused_batch_bj<T, 14>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
     default: return hipErrorInvalidValue;
     }

@@ -16,8 +16,9 @@ inline int vec_of(const hj_config& c) { return c.kernel == HJ_KERNEL_DIRECT ? 1 
 
 inline bool fused_of(const hj_config& c) { return c.tsteps == 2; }
 
-// Own k cells per tile of the two-iteration kernel (a 64-lane row minus its halo).
-constexpr int kFusedTK = kWave - 2;
+// Own k cells per tile of the two-iteration kernels: a 64-lane row minus its
+// halo (vec 1), or a whole 64-lane row with a halo wave beside it (vec 2).
+inline int fused_tk(const hj_config& c) { return c.vec == 2 ? kWave : kWave - 2; }
 
 // LDS bytes per staged plane of the flat kernel.
 constexpr int kFlatPlaneBytesHost = 10240;
@@ -36,7 +37,8 @@ inline TileCounts tile_counts(const hj_config& c, int nx, int ny, int nz)
 {
     TileCounts t;
     if (fused_of(c)) {
-        t.kt_n = (nz - 2 + kFusedTK - 1) / kFusedTK;
+        const int tk = fused_tk(c);
+        t.kt_n = (nz - 2 + tk - 1) / tk;
         t.jt_n = (ny - 2 + c.bj - 1) / c.bj;
         t.ic_n = chunks(nx, c.ichunk);
         return t;

@@ -617,6 +617,250 @@ __global__ __launch_bounds__(kWave * (BJ + 2)) __attribute__((amdgpu_waves_per_e
     fused_block<T, BJ, NT, KEEP>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
 }
 
+// ---- wide fused kernel: 64 own cells per row and a halo wave -----------------
+//
+// The same two iterations per pass, with tiles of BJ rows x 64 cells aligned
+// to the 64-lane rows (so a power-of-two interior width is tiled without a
+// ragged last tile). Waves 0 .. BJ+1 sit on rows j0-1 .. j0+BJ, lane l on
+// column k0+l; wave BJ+2 computes the first iteration on the two halo
+// columns k0-1 and k0+64 of those rows (lane 2r+s: row j0-1+r, side s) and
+// fetches the four p0 columns k0-2, k0-1, k0+64, k0+65 the others do not.
+template <typename T, int BJ>
+struct alignas(16) WideLds {
+    static constexpr int TK = kWave;       // own cells per row
+    static constexpr int R0 = BJ + 4;      // p0 rows j0-2 .. j0+BJ+1
+    static constexpr int W0 = kWave + 4;   // p0 cols k0-2 .. k0+65
+    static constexpr int R1 = BJ + 2;      // p1 rows j0-1 .. j0+BJ
+    static constexpr int W1 = kWave + 2;   // p1 cols k0-1 .. k0+64
+    static constexpr int NW = BJ + 3;      // waves
+    T p0[4][R0][W0];
+    T p1[4][R1][W1];
+    double red[NW];
+};
+
+template <typename T>
+struct WideRegs {
+    T own, lo, hi, col[2];
+};
+
+// Fetch p0 plane ii: row waves their row (and the outer rows j0-2, j0+BJ+1),
+// the halo wave the 4 (BJ+4) cells of the outer columns.
+template <typename T, int BJ>
+__device__ __forceinline__ void wide_fetch(const Grid<T>& g, int ii, int j0, int k0, WideRegs<T>& r)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const T* base = g.src + (long long)ii * g.S;
+    if (w <= BJ + 1) {
+        const int k = k0 + lane, j = j0 - 1 + w;
+        if (k <= g.nz - 1) {
+            if (j <= g.ny - 1) r.own = base[(long long)j * g.P + k];
+            if (w == 0 && j0 - 2 >= 0) r.lo = base[(long long)(j0 - 2) * g.P + k];
+            if (w == BJ + 1 && j0 + BJ + 1 <= g.ny - 1) r.hi = base[(long long)(j0 + BJ + 1) * g.P + k];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int t = lane + kWave * q;
+            if (t < 4 * (BJ + 4)) {
+                const int jj = j0 - 2 + (t >> 2), cc = t & 3;
+                const int kk = cc < 2 ? k0 - 2 + cc : k0 + 62 + cc;
+                if (jj >= 0 && jj <= g.ny - 1 && kk >= 0 && kk <= g.nz - 1) r.col[q] = base[(long long)jj * g.P + kk];
+            }
+        }
+    }
+}
+
+template <typename T, int BJ>
+__device__ __forceinline__ void wide_put(const Grid<T>& g, T (*pl)[WideLds<T, BJ>::W0], int j0, int k0,
+                                         const WideRegs<T>& r)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (w <= BJ + 1) {
+        const int k = k0 + lane, j = j0 - 1 + w;
+        if (k <= g.nz - 1) {
+            if (j <= g.ny - 1) pl[w + 1][lane + 2] = r.own;
+            if (w == 0 && j0 - 2 >= 0) pl[0][lane + 2] = r.lo;
+            if (w == BJ + 1 && j0 + BJ + 1 <= g.ny - 1) pl[BJ + 3][lane + 2] = r.hi;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int t = lane + kWave * q;
+            if (t < 4 * (BJ + 4)) {
+                const int jj = j0 - 2 + (t >> 2), cc = t & 3;
+                const int kk = cc < 2 ? k0 - 2 + cc : k0 + 62 + cc;
+                if (jj >= 0 && jj <= g.ny - 1 && kk >= 0 && kk <= g.nz - 1)
+                    pl[t >> 2][cc < 2 ? cc : kWave + cc] = r.col[q];
+            }
+        }
+    }
+}
+
+template <typename T, int BJ, bool NT, bool KEEP>
+__device__ __forceinline__ void wide_tile(const Grid<T>& g, T omega, int kt, int jt, int ib, int ie,
+                                          WideLds<T, BJ>& sm, double& acc1, double& acc2)
+{
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int k0 = 1 + kt * kWave, j0 = 1 + jt * BJ;
+    const bool halo = (w == BJ + 2);
+    // this thread's first-iteration cell, its place in the p0 and p1 tiles
+    int j, k, rho, c, r1, c1;
+    bool active;
+    if (!halo) {
+        j = j0 - 1 + w; k = k0 + lane; rho = w + 1; c = lane + 2; r1 = w; c1 = lane + 1; active = true;
+    } else {
+        const int rr = lane >> 1, side = lane & 1;
+        j = j0 - 1 + rr; k = side ? k0 + kWave : k0 - 1; rho = rr + 1; c = side ? kWave + 2 : 1;
+        r1 = rr; c1 = side ? kWave + 1 : 0; active = lane < 2 * (BJ + 2);
+    }
+    const bool in_dom = active && (j <= g.ny - 1) && (k <= g.nz - 1);
+    const bool jk_int = in_dom && j >= 1 && j <= g.ny - 2 && k >= 1 && k <= g.nz - 2;
+    const bool own = !halo && w >= 1 && w <= BJ;
+    const bool out = own && jk_int;                       // an output cell of this tile
+    const long long rowoff = (long long)j * g.P + k;
+
+    const int i_lo = ib - 1, i_hi = ie;                    // first-iteration planes
+    WideRegs<T> rr;
+    for (int ii = i_lo - 1; ii <= i_lo + 1; ++ii) {
+        if (ii < 0) continue;
+        wide_fetch<T, BJ>(g, ii, j0, k0, rr);
+        wide_put<T, BJ>(g, sm.p0[ii & 3], j0, k0, rr);
+    }
+    __syncthreads();
+
+    T keep[KEEP ? NCOEF : 1];          // own cell's coefficients of the previous plane
+#pragma unroll
+    for (int q = 0; q < (KEEP ? NCOEF : 1); ++q) keep[q] = T(0);
+    for (int i = i_lo; i <= i_hi; ++i) {
+        const bool more = (i + 2 <= i_hi + 1) && (i + 2 <= g.nx - 1);
+        if (more) wide_fetch<T, BJ>(g, i + 2, j0, k0, rr);
+
+        // ---- first iteration at plane i
+        T cur[NCOEF];
+        const bool interior = jk_int && i >= 1 && i <= g.nx - 2;
+        if (in_dom) {
+            auto* Pm = sm.p0[(i - 1) & 3];
+            auto* Pc = sm.p0[i & 3];
+            auto* Pp = sm.p0[(i + 1) & 3];
+            T p1v;
+            if (interior) {
+                const long long o = (long long)i * g.S + rowoff;
+#pragma unroll
+                for (int q = 0; q < NCOEF; ++q) cur[q] = sload<T, NT>(g.coef[q] + o);
+                const T pc = Pc[rho][c];
+                const T ss = cell_ss<T>(cur[CA0], cur[CA1], cur[CA2], cur[CA3], cur[CB0], cur[CB1], cur[CB2],
+                                        cur[CC0], cur[CC1], cur[CC2], cur[CBND], cur[CWRK1],
+                                        Pp[rho][c], Pc[rho + 1][c], Pc[rho][c + 1],
+                                        bracket(Pp[rho + 1][c], Pp[rho - 1][c], Pm[rho + 1][c], Pm[rho - 1][c]),
+                                        bracket(Pc[rho + 1][c + 1], Pc[rho - 1][c + 1], Pc[rho + 1][c - 1],
+                                                Pc[rho - 1][c - 1]),
+                                        bracket(Pp[rho][c + 1], Pm[rho][c + 1], Pp[rho][c - 1], Pm[rho][c - 1]),
+                                        Pm[rho][c], Pc[rho - 1][c], Pc[rho][c - 1], pc);
+                p1v = pc + omega * ss;
+                if (out && i >= ib && i < ie) {
+                    const double d = (double)ss;
+                    acc1 += d * d;
+                }
+            } else {
+                p1v = Pc[rho][c];                              // the shell is never updated
+            }
+            sm.p1[i & 3][r1][c1] = p1v;
+        }
+        if (more) wide_put<T, BJ>(g, sm.p0[(i + 2) & 3], j0, k0, rr);
+        __syncthreads();
+
+        // ---- second iteration at plane i-1, own cells
+        const int i2 = i - 1;
+        if (out && i2 >= ib && i2 < ie) {
+            auto* Qm = sm.p1[(i2 - 1) & 3];
+            auto* Qc = sm.p1[i2 & 3];
+            auto* Qp = sm.p1[(i2 + 1) & 3];
+            const T qc = Qc[r1][c1];
+            T kc[NCOEF];
+            if constexpr (KEEP) {
+#pragma unroll
+                for (int q = 0; q < NCOEF; ++q) kc[q] = keep[q];
+            } else {
+                const long long o2 = (long long)i2 * g.S + rowoff;
+#pragma unroll
+                for (int q = 0; q < NCOEF; ++q) kc[q] = g.coef[q][o2];
+            }
+            const T ss = cell_ss<T>(kc[CA0], kc[CA1], kc[CA2], kc[CA3], kc[CB0], kc[CB1], kc[CB2],
+                                    kc[CC0], kc[CC1], kc[CC2], kc[CBND], kc[CWRK1],
+                                    Qp[r1][c1], Qc[r1 + 1][c1], Qc[r1][c1 + 1],
+                                    bracket(Qp[r1 + 1][c1], Qp[r1 - 1][c1], Qm[r1 + 1][c1], Qm[r1 - 1][c1]),
+                                    bracket(Qc[r1 + 1][c1 + 1], Qc[r1 - 1][c1 + 1], Qc[r1 + 1][c1 - 1],
+                                            Qc[r1 - 1][c1 - 1]),
+                                    bracket(Qp[r1][c1 + 1], Qm[r1][c1 + 1], Qp[r1][c1 - 1], Qm[r1][c1 - 1]),
+                                    Qm[r1][c1], Qc[r1 - 1][c1], Qc[r1][c1 - 1], qc);
+            const T outv = qc + omega * ss;
+            T* dst = g.dst + (long long)i2 * g.S + rowoff;
+            if constexpr (NT) __builtin_nontemporal_store(outv, dst);
+            else *dst = outv;
+            const double d = (double)ss;
+            acc2 += d * d;
+        }
+        if constexpr (KEEP) {
+            if (interior) {
+#pragma unroll
+                for (int q = 0; q < NCOEF; ++q) keep[q] = cur[q];
+            }
+        }
+    }
+}
+
+template <typename T, int BJ, bool NT, bool KEEP>
+__device__ __forceinline__ void wide_block(const Grid<T>& g, T omega, int kt, int jt, int ic, int ichunk, int L,
+                                           WideLds<T, BJ>& sm, double* __restrict__ part1,
+                                           double* __restrict__ part2)
+{
+    const int ib = 1 + ic * ichunk;
+    int ie = ib + ichunk;
+    if (ie > g.nx - 1) ie = g.nx - 1;
+    double acc1 = 0.0, acc2 = 0.0;
+    wide_tile<T, BJ, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
+    acc1 = block_sum<BJ + 3>(acc1, sm.red);
+    if (threadIdx.x == 0) part1[L] = acc1;
+    acc2 = block_sum<BJ + 3>(acc2, sm.red);
+    if (threadIdx.x == 0) part2[L] = acc2;
+}
+
+template <typename T, int BJ, bool NT, bool KEEP>
+__global__ __launch_bounds__(kWave * (BJ + 3)) void wide_kernel(Grid<T> g, T omega, int ichunk, int kt_n, int jt_n,
+                                                                int remap, double* __restrict__ part1,
+                                                                double* __restrict__ part2)
+{
+    __shared__ WideLds<T, BJ> sm;
+    const int L = remap_xcd(blockIdx.x, gridDim.x, remap);
+    const int kt = L % kt_n;
+    const int jt = (L / kt_n) % jt_n;
+    const int ic = L / (kt_n * jt_n);
+    wide_block<T, BJ, NT, KEEP>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
+}
+
+template <typename T, int BJ, bool NT, bool KEEP>
+__global__ __launch_bounds__(kWave * (BJ + 3)) void wide_batch_kernel(const Instance<T>* __restrict__ inst,
+                                                                      const int* __restrict__ tile_inst, int parity,
+                                                                      T omega, int remap,
+                                                                      double* __restrict__ part1,
+                                                                      double* __restrict__ part2)
+{
+    __shared__ WideLds<T, BJ> sm;
+    const int L = remap_xcd(blockIdx.x, gridDim.x, remap);
+    const Instance<T>& d = inst[tile_inst[L]];
+    Grid<T> g;
+#pragma unroll
+    for (int q = 0; q < NCOEF; ++q) g.coef[q] = d.coef[q];
+    g.src = d.f[parity];
+    g.dst = d.f[parity ^ 1];
+    g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.P = d.P; g.S = d.S;
+    const int t = L - d.tile0;
+    const int kt = t % d.kt_n;
+    const int jt = (t / d.kt_n) % d.jt_n;
+    const int ic = t / (d.kt_n * d.jt_n);
+    wide_block<T, BJ, NT, KEEP>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
+}
+
 // ---- flat kernel: tiles of consecutive interior (j,k) cells -------------------
 //
 // A tile is a run of T = 64*NW consecutive cells of the flattened interior

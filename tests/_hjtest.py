@@ -90,6 +90,9 @@ def fused_configs():
     for bj in (2, 4, 6, 8, 14):
         for ich, nt, rm, rr in ((1, 1, 0, 0), (2, 0, 1, 1), (5, 1, 0, 1), (1000, 0, 1, 0)):
             out.append(cfg(bj=bj, vec=1, ichunk=ich, nontemporal=nt, xcd_remap=rm, tsteps=2, reread=rr))
+    for bj in (2, 4, 6, 8, 12):          # 64-cell rows with a halo wave
+        for ich, nt, rm, rr in ((1, 0, 1, 0), (3, 1, 0, 1), (1000, 0, 1, 1)):
+            out.append(cfg(bj=bj, vec=2, ichunk=ich, nontemporal=nt, xcd_remap=rm, tsteps=2, reread=rr))
     return out
 
 
@@ -107,5 +110,5 @@ def f32_configs():
 def cfg_id(c):
     d = c.as_dict()
     k = ("direct" if d["kernel"] == 0 else "flat" if d["kernel"] == 2 else
-         "fused%d" % d["reread"] if d["tsteps"] == 2 else "march")
+         ("wide%d" if d["vec"] == 2 else "fused%d") % d["reread"] if d["tsteps"] == 2 else "march")
     return "%s-bj%d-v%d-ic%d-nt%d-rm%d" % (k, d["bj"], d["vec"], d["ichunk"], d["nontemporal"], d["xcd_remap"])

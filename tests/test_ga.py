@@ -180,11 +180,17 @@ def test_gene_decoding(lib):
     # folded codes: vec code 2 is 1 for FP64 and 4 for FP32; direct reads bj 1 as 2
     assert dec(0, 1 | (2 << 3))["vec"] == 1 and dec(1, 1 | (2 << 3))["vec"] == 4
     assert dec(0, 0)["bj"] == 2 and dec(0, 0)["kernel"] == 0
-    # two iterations per pass: march only, vec 1, bj codes read as 14, 6, 4, 8
-    d = dec(0, 1 | (1 << 10) | (3 << 3))
+    # two iterations per pass: march only, bj codes read as 14, 6, 4, 8; bit 3
+    # reread, bit 4 the 64-cell rows (vec 2), where bj 14 reads as 12
+    d = dec(0, 1 | (1 << 10) | (1 << 3))
     assert (d["tsteps"], d["vec"], d["bj"], d["reread"]) == (2, 1, 14, 1)
+    d = dec(0, 1 | (1 << 10) | (3 << 3))
+    assert (d["tsteps"], d["vec"], d["bj"], d["reread"]) == (2, 2, 12, 1)
     assert dec(0, 1 | (1 << 10) | (2 << 3))["reread"] == 0
     assert [dec(0, 1 | (1 << 10) | (b << 1))["bj"] for b in range(4)] == [14, 6, 4, 8]
+    assert [dec(0, 1 | (1 << 10) | (2 << 3) | (b << 1))["bj"] for b in range(4)] == [12, 6, 4, 8]
+    # the 64-cell rows tile a 256-wide interior in 4: the chunks fit 256 workgroups in 4 x 16 x 4
+    assert dec(0, 1 | (1 << 10) | (2 << 3) | (3 << 1))["ichunk"] == 32
     # their chunks: the longest within 256, 512, ... workgroups (5 x 16 tiles of bj 8 here)
     fch = [dec(0, 1 | (1 << 10) | (3 << 1) | (sel << 5))["ichunk"] for sel in range(8)]
     assert fch[:4] == [43, 22, 15, 11]

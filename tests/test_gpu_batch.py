@@ -34,6 +34,10 @@ def batch_configs(dtype):
         for ich, rr, rm in ((1, 0, 0), (5, 1, 1), (64, 0, 1)):
             out.append(hj.Config.make(kernel=1, bj=bj, vec=1, ichunk=ich, nontemporal=0, use_graph=1,
                                       xcd_remap=rm, persistent=0, tsteps=2, reread=rr))
+    for bj in (2, 6, 12):                       # two iterations, 64-cell rows with a halo wave
+        for ich, rr, rm in ((1, 1, 1), (7, 0, 0), (64, 1, 0)):
+            out.append(hj.Config.make(kernel=1, bj=bj, vec=2, ichunk=ich, nontemporal=0, use_graph=1,
+                                      xcd_remap=rm, persistent=0, tsteps=2, reread=rr))
     return out
 
 
@@ -87,7 +91,7 @@ def test_two_iteration_batch_odd_counts_and_residual(dtype):
     gosa history continue across calls, as for single solves."""
     shapes, seeds = inputs.batch_shapes(11, 6, lo_xy=5, hi_xy=40, lo_z=5, hi_z=150)
     arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
-    c = hj.Config.make(kernel=1, bj=6, vec=1, ichunk=7, nontemporal=0, use_graph=1, xcd_remap=1, persistent=0,
+    c = hj.Config.make(kernel=1, bj=6, vec=2, ichunk=7, nontemporal=0, use_graph=1, xcd_remap=1, persistent=0,
                        tsteps=2, reread=0)
     say("two-iteration batch, odd counts", dtype)
     with hj.Batch(dtype, shapes) as b:
