@@ -83,6 +83,13 @@ def esize(dtype: str) -> int:
     return 8 if dtype == "f64" else 4
 
 
+def kernel_name(cfg: dict) -> str:
+    """The kernel a configuration launches for its passes."""
+    if cfg.get("tsteps") == 2:
+        return "wide_kernel" if cfg.get("vec") == 2 else "fused_kernel"
+    return {0: "direct_kernel", 1: "march_kernel", 2: "flat_kernel"}[cfg["kernel"]]
+
+
 def load_traffic(workload: str, cfg: dict):
     """HBM bytes per launch measured by rocprofv3 counters, if they were taken
     on the current kernel sources and the same launch configuration."""
@@ -166,7 +173,16 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
     log("inputs generated in %.1f s, uploaded in %.2f s" % (gen_s, upload_s))
     tuned_ms = None
     key = "%dx%dx%d" % tuple(w.shape)
-    if args.retune or not cache_has("solve", w.dtype, key):
+    if args.config and w.name == args.workload:
+        c = s.config.as_dict()
+        for kv in args.config.split(","):
+            k, v = kv.split("=")
+            if k not in c:
+                raise SystemExit("--config: unknown field %r" % k)
+            c[k] = int(v)
+        s.config = hj.Config.make(**c)
+        log("configuration from --config:", s.config)
+    elif args.retune or not cache_has("solve", w.dtype, key):
         c, tuned_ms = s.autotune(n_sweeps=args.tune_sweeps, repeats=3)
         log("autotuned:", c, "%.3f ms per %d sweeps" % (tuned_ms, args.tune_sweeps))
     else:
@@ -374,6 +390,9 @@ def main():
     ap.add_argument("--no-ceilings", dest="ceilings", action="store_false",
                     help="skip the copy and 13-read/1-write bandwidth probes")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--config", default="",
+                    help="run the main workload in this configuration instead of the tuned one, "
+                         "as field=value pairs, e.g. tsteps=1,vec=2,bj=4,ichunk=2,nontemporal=1")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: no oracle, no extras")
     args = ap.parse_args()
@@ -429,8 +448,7 @@ def main():
                    "omega": w.omega, "seed": w.seed, "kernel_config": res["config"]},
         "roofline": {"bound": "hbm", "achieved": res["hbm_gbps_alg"], "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": res["frac_peak"], "traffic": res["traffic"],
-                     "kernel": ("direct_kernel" if res["config"]["kernel"] == 0 else
-                                "fused_kernel" if res["config"].get("tsteps") == 2 else "march_kernel"),
+                     "kernel": kernel_name(res["config"]),
                      "lattice_updates_per_launch": interior(w.shape) * (2 if res["config"].get("tsteps") == 2 else 1),
                      "bytes_per_launch": res["bytes_per_launch"],
                      "avg_launch_ms": res["avg_launch_ms"], "measured_ceilings": res["ceilings"]},
