@@ -482,12 +482,25 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
     T keep[KEEP ? NCOEF : 1];          // own cell's coefficients of the previous plane
 #pragma unroll
     for (int q = 0; q < (KEEP ? NCOEF : 1); ++q) keep[q] = T(0);
+    // the coefficients of plane i are loaded one step ahead, so their loads
+    // are in flight while plane i-1 is computed and the workgroup waits
+    T cur[NCOEF];
+    if (jk_int && i_lo >= 1 && i_lo <= g.nx - 2) {
+        const long long o = (long long)i_lo * g.S + rowoff;
+#pragma unroll
+        for (int q = 0; q < NCOEF; ++q) cur[q] = sload<T, NT>(g.coef[q] + o);
+    }
     for (int i = i_lo; i <= i_hi; ++i) {
         const bool more = (i + 2 <= i_hi + 1) && (i + 2 <= g.nx - 1);
         if (more) fused_fetch<T, BJ>(g, i + 2, j0, k0, rr);
+        T nxt[NCOEF];
+        if (jk_int && i + 1 <= i_hi && i + 1 <= g.nx - 2) {
+            const long long o = (long long)(i + 1) * g.S + rowoff;
+#pragma unroll
+            for (int q = 0; q < NCOEF; ++q) nxt[q] = sload<T, NT>(g.coef[q] + o);
+        }
 
         // ---- first iteration at plane i, extended cell (j, k)
-        T cur[NCOEF];
         const bool interior = jk_int && i >= 1 && i <= g.nx - 2;
         if (in_dom) {
             auto* Pm = sm.p0[(i - 1) & 3];
@@ -495,9 +508,6 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
             auto* Pp = sm.p0[(i + 1) & 3];
             T p1v;
             if (interior) {
-                const long long o = (long long)i * g.S + rowoff;
-#pragma unroll
-                for (int q = 0; q < NCOEF; ++q) cur[q] = sload<T, NT>(g.coef[q] + o);
                 const T pc = Pc[rho][c];
                 const T ss = cell_ss<T>(cur[CA0], cur[CA1], cur[CA2], cur[CA3], cur[CB0], cur[CB1], cur[CB2],
                                         cur[CC0], cur[CC1], cur[CC2], cur[CBND], cur[CWRK1],
@@ -557,6 +567,8 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
                 for (int q = 0; q < NCOEF; ++q) keep[q] = cur[q];
             }
         }
+#pragma unroll
+        for (int q = 0; q < NCOEF; ++q) cur[q] = nxt[q];
     }
 }
 
@@ -731,12 +743,25 @@ __device__ __forceinline__ void wide_tile(const Grid<T>& g, T omega, int kt, int
     T keep[KEEP ? NCOEF : 1];          // own cell's coefficients of the previous plane
 #pragma unroll
     for (int q = 0; q < (KEEP ? NCOEF : 1); ++q) keep[q] = T(0);
+    // the coefficients of plane i are loaded one step ahead, so their loads
+    // are in flight while plane i-1 is computed and the workgroup waits
+    T cur[NCOEF];
+    if (jk_int && i_lo >= 1 && i_lo <= g.nx - 2) {
+        const long long o = (long long)i_lo * g.S + rowoff;
+#pragma unroll
+        for (int q = 0; q < NCOEF; ++q) cur[q] = sload<T, NT>(g.coef[q] + o);
+    }
     for (int i = i_lo; i <= i_hi; ++i) {
         const bool more = (i + 2 <= i_hi + 1) && (i + 2 <= g.nx - 1);
         if (more) wide_fetch<T, BJ>(g, i + 2, j0, k0, rr);
+        T nxt[NCOEF];
+        if (jk_int && i + 1 <= i_hi && i + 1 <= g.nx - 2) {
+            const long long o = (long long)(i + 1) * g.S + rowoff;
+#pragma unroll
+            for (int q = 0; q < NCOEF; ++q) nxt[q] = sload<T, NT>(g.coef[q] + o);
+        }
 
         // ---- first iteration at plane i
-        T cur[NCOEF];
         const bool interior = jk_int && i >= 1 && i <= g.nx - 2;
         if (in_dom) {
             auto* Pm = sm.p0[(i - 1) & 3];
@@ -744,9 +769,6 @@ __device__ __forceinline__ void wide_tile(const Grid<T>& g, T omega, int kt, int
             auto* Pp = sm.p0[(i + 1) & 3];
             T p1v;
             if (interior) {
-                const long long o = (long long)i * g.S + rowoff;
-#pragma unroll
-                for (int q = 0; q < NCOEF; ++q) cur[q] = sload<T, NT>(g.coef[q] + o);
                 const T pc = Pc[rho][c];
                 const T ss = cell_ss<T>(cur[CA0], cur[CA1], cur[CA2], cur[CA3], cur[CB0], cur[CB1], cur[CB2],
                                         cur[CC0], cur[CC1], cur[CC2], cur[CBND], cur[CWRK1],
@@ -806,6 +828,8 @@ __device__ __forceinline__ void wide_tile(const Grid<T>& g, T omega, int kt, int
                 for (int q = 0; q < NCOEF; ++q) keep[q] = cur[q];
             }
         }
+#pragma unroll
+        for (int q = 0; q < NCOEF; ++q) cur[q] = nxt[q];
     }
 }
 
