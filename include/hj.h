@@ -79,11 +79,13 @@ enum hj_field {
  * tsteps: Jacobi iterations per pass over memory. 1, or 2: the march
  * kernel computes the first iteration of a tile and its one-cell halo into
  * LDS and the second from it, so each coefficient is read once per two
- * iterations. Needs kernel HJ_KERNEL_MARCH, not persistent, and vec 1
- * (tiles of 62-cell rows, each a 64-lane row with its halo; bj 2, 4, 6, 8
- * or 14) or vec 2 (tiles of 64-cell rows, one more wave computing the halo
- * columns; bj 2, 4, 6, 8 or 12). An odd remainder runs one single-iteration
- * launch. 0 means 1. The results are bitwise those of tsteps 1.
+ * iterations. Needs kernel HJ_KERNEL_MARCH, not persistent, and a row
+ * layout in vec: 1, tiles of 62-cell rows, each a 64-lane row with its halo
+ * (bj 2, 4, 6, 8 or 14; bj+2 waves); 2, tiles of 64-cell rows, one more
+ * wave computing the halo columns (bj 2, 4, 6, 8 or 12; bj+3 waves); 4,
+ * tiles of 30-cell rows, two 32-lane rows per wave (bj 6, 14, 22 or 30;
+ * (bj+2)/2 waves). An odd remainder runs one single-iteration launch. 0
+ * means 1. The results are bitwise those of tsteps 1.
  * reread (tsteps 2 only): 0 holds each cell's coefficients in registers
  * between its two iterations, 1 reads them again for the second (an L2 hit
  * when nontemporal is 0), which frees registers for more resident waves. */
@@ -184,7 +186,8 @@ int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long l
  * kernel reads 1 as 2; two-iteration passes read the codes as 14, 6, 4, 8).
  * bits 3-4: vec 1, 2, 1, 2 (FP64) or 1, 2, 4, 4 (FP32) for the
  * one-iteration march kernel; for two-iteration passes bit 3 is reread and
- * bit 4 selects vec 2 (where bj 14 reads as 12).
+ * bit 4 the row layout: vec 2 for single solves (where bj 14 reads as 12),
+ * vec 4 for batches (bj codes 14, 6, 22, 30).
  * bits 5-7: the i-chunk n, giving about 512 << n workgroups; for
  * two-iteration passes the longest chunk within 256, 512, 768, 1024, 2048,
  * 4096, 8192 or 24576 workgroups; for batches 2^n planes (one-iteration)

@@ -520,8 +520,10 @@ struct Evaluator {
 //              10 two iterations per pass)
 //   bits 1-2   bj: 1, 2, 4, 8 (direct: 1 reads as 2; two-iteration: 14, 6, 4, 8)
 //   bits 3-4   vec (march, one iteration): FP64 1, 2, 1, 2; FP32 1, 2, 4, 4;
-//              two-iteration passes: bit 3 is reread, bit 4 the 64-cell rows
-//              with a halo wave (vec 2, where bj 14 reads as 12)
+//              two-iteration passes: bit 3 is reread, bit 4 the row layout:
+//              single solves 64-cell rows with a halo wave (vec 2, where bj
+//              14 reads as 12), batches two 30-cell rows per wave (vec 4,
+//              bj codes 14, 6, 22, 30)
 //   bits 5-7   one of 8 i-chunk lengths (march kernels)
 //   bit 8      non-temporal streams
 //   bit 9      XCD renumbering (single solves, two-iteration batches) /
@@ -544,7 +546,7 @@ int gene_ichunk(int sel, const hj_config& c, int nx, int ny, int nz)
 
 bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_config& c)
 {
-    static const int kBj[4] = {1, 2, 4, 8}, kBjFused[4] = {14, 6, 4, 8};
+    static const int kBj[4] = {1, 2, 4, 8}, kBjFused[4] = {14, 6, 4, 8}, kBjNarrow[4] = {14, 6, 22, 30};
     static const int kVec64[4] = {1, 2, 1, 2}, kVec32[4] = {1, 2, 4, 4};
     c = default_config(dtype);
     const int b0 = g & 1, b10 = (g >> 10) & 1;
@@ -572,8 +574,9 @@ bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_c
         c.ichunk = 1;
     } else if (c.tsteps == 2) {
         c.bj = kBjFused[bi];
-        c.vec = (vi >> 1) ? 2 : 1;
+        c.vec = (vi >> 1) ? (batch ? 4 : 2) : 1;
         if (c.vec == 2 && c.bj == 14) c.bj = 12;
+        if (c.vec == 4) c.bj = kBjNarrow[bi];
         c.reread = vi & 1;
         c.ichunk = batch ? (4 << sel) : gene_ichunk(sel, c, nx, ny, nz);
     } else {
@@ -956,7 +959,8 @@ std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch,
         // wave): long chunks (the halo planes of a chunk are recomputed), sized
         // to 1 .. 64 waves of resident workgroups; XCD renumbering lets
         // neighbouring tiles share their halo reads in L2
-        static const std::pair<int, int> kFusedShapes[] = {{1, 6}, {1, 8}, {1, 14}, {2, 4}, {2, 6}, {2, 8}, {2, 12}};
+        static const std::pair<int, int> kFusedShapes[] = {{1, 6},  {1, 8},  {1, 14}, {2, 4},  {2, 6},
+                                                           {2, 8},  {2, 12}, {4, 14}, {4, 30}};
         for (const auto& vb : kFusedShapes)
             for (int rr : {0, 1})
                 for (int rm : {1}) {
@@ -1947,7 +1951,8 @@ std::vector<hj_config> batch_candidates(const hj_batch_s* b)
                         if (config_supported(dtype, c)) out.push_back(c);
                     }
     // two iterations per pass, one workgroup per tile, XCD renumbering
-    static const std::pair<int, int> kFusedShapes[] = {{1, 6}, {1, 8}, {1, 14}, {2, 4}, {2, 6}, {2, 8}, {2, 12}};
+    static const std::pair<int, int> kFusedShapes[] = {{1, 6}, {1, 8},  {1, 14}, {2, 6},  {2, 8},
+                                                       {2, 12}, {4, 6}, {4, 14}, {4, 22}, {4, 30}};
     for (const auto& vb : kFusedShapes)
         for (int ich : {8, 12, 16, 24, 32, 48, 64, 128})
             for (int rr : {0, 1}) {

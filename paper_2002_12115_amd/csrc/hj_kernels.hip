@@ -2,6 +2,8 @@
 #include "hj_launch.hpp"
 #include "sweep_kernels.hpp"
 
+#include <type_traits>
+
 namespace hj {
 
 namespace {
@@ -117,12 +119,8 @@ bool config_supported(int dtype, const hj_config& c)
     if (dtype != HJ_F64 && dtype != HJ_F32) return false;
     if (c.tsteps < 0 || c.tsteps > 2 || c.reread < 0 || c.reread > 1) return false;
     if (c.xcd_remap < 0 || c.xcd_remap > 1) return false;
-    if (c.tsteps == 2) {
-        if (c.kernel != HJ_KERNEL_MARCH || c.ichunk < 1 || c.persistent != 0) return false;
-        if (c.vec == 1) return c.bj == 2 || c.bj == 4 || c.bj == 6 || c.bj == 8 || c.bj == 14;
-        if (c.vec == 2) return c.bj == 2 || c.bj == 4 || c.bj == 6 || c.bj == 8 || c.bj == 12;
-        return false;
-    }
+    if (c.tsteps == 2)
+        return c.kernel == HJ_KERNEL_MARCH && c.ichunk >= 1 && c.persistent == 0 && fused_bj_ok(c.vec, c.bj);
     if (c.kernel == HJ_KERNEL_FLAT) return (c.bj == 2 || c.bj == 4 || c.bj == 8) && c.vec == 1 && c.ichunk >= 1;
     if (!bj_ok(c.bj)) return false;
     if (c.kernel == HJ_KERNEL_DIRECT) return c.bj >= 2;
@@ -251,7 +249,7 @@ int batch_occupancy(const hj_config& c)
 
 namespace {
 
-template <typename T, int BJ, bool NT, bool KEEP>
+template <typename T, int BJ, int W, bool NT, bool KEEP>
 hipError_t fused_go(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                     hipStream_t st)
 {
@@ -259,18 +257,19 @@ hipError_t fused_go(const hj_config& c, const Grid<T>& g, T omega, double* part1
     const long long nb = t.tiles();
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((fused_kernel<T, BJ, NT, KEEP>), dim3((unsigned)nb), dim3(kWave * (BJ + 2)), 0, st, g, omega,
+    hipLaunchKernelGGL((fused_kernel<T, BJ, W, NT, KEEP>), dim3((unsigned)nb), dim3(fused_threads<BJ, W>()), 0, st,
+                       g, omega,
                        c.ichunk, t.kt_n, t.jt_n, c.xcd_remap, part1, part2);
     return hipGetLastError();
 }
 
-template <typename T, int BJ, bool NT, bool KEEP>
+template <typename T, int BJ, int W, bool NT, bool KEEP>
 hipError_t fused_batch_go(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
                           int parity, T omega, double* part1, double* part2, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((fused_batch_kernel<T, BJ, NT, KEEP>), dim3((unsigned)ntiles), dim3(kWave * (BJ + 2)), 0,
-                       st, inst, tile_inst, parity, omega, c.xcd_remap, part1, part2);
+    hipLaunchKernelGGL((fused_batch_kernel<T, BJ, W, NT, KEEP>), dim3((unsigned)ntiles),
+                       dim3(fused_threads<BJ, W>()), 0, st, inst, tile_inst, parity, omega, c.xcd_remap, part1, part2);
     return hipGetLastError();
 }
 
@@ -296,102 +295,75 @@ hipError_t wide_batch_go(const hj_config& c, const Instance<T>* inst, const int*
     return hipGetLastError();
 }
 
+// Calls f(nt, keep) with std::bool_constant arguments for the streaming
+// mode (nontemporal) and coefficient mode (KEEP = !reread) of c.
+template <typename F>
+auto with_modes(const hj_config& c, F&& f)
+{
+    if (c.reread) return c.nontemporal ? f(std::true_type{}, std::false_type{}) : f(std::false_type{}, std::false_type{});
+    return c.nontemporal ? f(std::true_type{}, std::true_type{}) : f(std::false_type{}, std::true_type{});
+}
+
 template <typename T, int BJ>
 hipError_t fused_batch_bj(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
                           int parity, T omega, double* part1, double* part2, hipStream_t st)
 {
-    if (c.vec == 2) {
-        if constexpr (BJ + 3 <= 16) {
-            if (c.reread)
-                return c.nontemporal
-                           ? wide_batch_go<T, BJ, true, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
-                           : wide_batch_go<T, BJ, false, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2,
-                                                                st);
-            return c.nontemporal
-                       ? wide_batch_go<T, BJ, true, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
-                       : wide_batch_go<T, BJ, false, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
-        } else {
-            return hipErrorInvalidValue;
+    return with_modes(c, [&](auto nt, auto keep) -> hipError_t {
+        constexpr bool NT = decltype(nt)::value, KEEP = decltype(keep)::value;
+        if (c.vec == 1) {
+            if constexpr (fused_bj_ok(1, BJ))
+                return fused_batch_go<T, BJ, kWave, NT, KEEP>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+        } else if (c.vec == 2) {
+            if constexpr (fused_bj_ok(2, BJ))
+                return wide_batch_go<T, BJ, NT, KEEP>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+        } else if (c.vec == 4) {
+            if constexpr (fused_bj_ok(4, BJ))
+                return fused_batch_go<T, BJ, kWave / 2, NT, KEEP>(c, inst, tile_inst, ntiles, parity, omega, part1,
+                                                                 part2, st);
         }
-    }
-    if constexpr (BJ + 2 <= 16) {
-        if (c.reread)
-            return c.nontemporal
-                       ? fused_batch_go<T, BJ, true, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
-                       : fused_batch_go<T, BJ, false, false>(c, inst, tile_inst, ntiles, parity, omega, part1, part2,
-                                                             st);
-        return c.nontemporal
-                   ? fused_batch_go<T, BJ, true, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st)
-                   : fused_batch_go<T, BJ, false, true>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
-    } else {
         return hipErrorInvalidValue;
-    }
+    });
 }
 
 template <typename T, int BJ>
 hipError_t fused_bj(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                     hipStream_t st)
 {
-    if (c.vec == 2) {
-        if constexpr (BJ + 3 <= 16) {
-            if (c.reread)
-                return c.nontemporal ? wide_go<T, BJ, true, false>(c, g, omega, part1, part2, st)
-                                     : wide_go<T, BJ, false, false>(c, g, omega, part1, part2, st);
-            return c.nontemporal ? wide_go<T, BJ, true, true>(c, g, omega, part1, part2, st)
-                                 : wide_go<T, BJ, false, true>(c, g, omega, part1, part2, st);
-        } else {
-            return hipErrorInvalidValue;
+    return with_modes(c, [&](auto nt, auto keep) -> hipError_t {
+        constexpr bool NT = decltype(nt)::value, KEEP = decltype(keep)::value;
+        if (c.vec == 1) {
+            if constexpr (fused_bj_ok(1, BJ)) return fused_go<T, BJ, kWave, NT, KEEP>(c, g, omega, part1, part2, st);
+        } else if (c.vec == 2) {
+            if constexpr (fused_bj_ok(2, BJ)) return wide_go<T, BJ, NT, KEEP>(c, g, omega, part1, part2, st);
+        } else if (c.vec == 4) {
+            if constexpr (fused_bj_ok(4, BJ))
+                return fused_go<T, BJ, kWave / 2, NT, KEEP>(c, g, omega, part1, part2, st);
         }
-    }
-    if constexpr (BJ + 2 <= 16) {
-        if (c.reread) {
-            return c.nontemporal ? fused_go<T, BJ, true, false>(c, g, omega, part1, part2, st)
-                                 : fused_go<T, BJ, false, false>(c, g, omega, part1, part2, st);
-        }
-        return c.nontemporal ? fused_go<T, BJ, true, true>(c, g, omega, part1, part2, st)
-                             : fused_go<T, BJ, false, true>(c, g, omega, part1, part2, st);
-    } else {
         return hipErrorInvalidValue;
-    }
-}
-
-template <typename T, int BJ, bool NT, bool KEEP>
-int fused_occ()
-{
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_kernel<T, BJ, NT, KEEP>, kWave * (BJ + 2), 0) !=
-        hipSuccess)
-        return 0;
-    return n;
-}
-
-template <typename T, int BJ, bool NT, bool KEEP>
-int wide_occ()
-{
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wide_kernel<T, BJ, NT, KEEP>, kWave * (BJ + 3), 0) !=
-        hipSuccess)
-        return 0;
-    return n;
+    });
 }
 
 template <typename T, int BJ>
 int fused_occ_bj(const hj_config& c)
 {
-    if (c.vec == 2) {
-        if constexpr (BJ + 3 <= 16) {
-            if (c.reread) return c.nontemporal ? wide_occ<T, BJ, true, false>() : wide_occ<T, BJ, false, false>();
-            return c.nontemporal ? wide_occ<T, BJ, true, true>() : wide_occ<T, BJ, false, true>();
-        } else {
-            return 0;
+    return with_modes(c, [&](auto nt, auto keep) -> int {
+        constexpr bool NT = decltype(nt)::value, KEEP = decltype(keep)::value;
+        int n = 0;
+        hipError_t e = hipErrorInvalidValue;
+        if (c.vec == 1) {
+            if constexpr (fused_bj_ok(1, BJ))
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_kernel<T, BJ, kWave, NT, KEEP>,
+                                                                 fused_threads<BJ, kWave>(), 0);
+        } else if (c.vec == 2) {
+            if constexpr (fused_bj_ok(2, BJ))
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wide_kernel<T, BJ, NT, KEEP>, kWave * (BJ + 3), 0);
+        } else if (c.vec == 4) {
+            if constexpr (fused_bj_ok(4, BJ))
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fused_kernel<T, BJ, kWave / 2, NT, KEEP>,
+                                                                 fused_threads<BJ, kWave / 2>(), 0);
         }
-    }
-    if constexpr (BJ + 2 <= 16) {
-        if (c.reread) return c.nontemporal ? fused_occ<T, BJ, true, false>() : fused_occ<T, BJ, false, false>();
-        return c.nontemporal ? fused_occ<T, BJ, true, true>() : fused_occ<T, BJ, false, true>();
-    } else {
-        return 0;
-    }
+        return e == hipSuccess ? n : 0;
+    });
 }
 
 }  // namespace
@@ -407,6 +379,8 @@ int fused_occupancy(const hj_config& c)
     case 8: return fused_occ_bj<T, 8>(c);
     case 12: return fused_occ_bj<T, 12>(c);
     case 14: return fused_occ_bj<T, 14>(c);
+    case 22: return fused_occ_bj<T, 22>(c);
+    case 30: return fused_occ_bj<T, 30>(c);
     default: return 0;
     }
 }
@@ -418,7 +392,7 @@ template <typename T>
 hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                         hipStream_t st)
 {
-    if (!fused_of(c) || c.kernel != HJ_KERNEL_MARCH || (c.vec != 1 && c.vec != 2) || c.ichunk < 1)
+    if (!fused_of(c) || c.kernel != HJ_KERNEL_MARCH || !fused_bj_ok(c.vec, c.bj) || c.ichunk < 1)
         return hipErrorInvalidValue;
     switch (c.bj) {
     case 2: return fused_bj<T, 2>(c, g, omega, part1, part2, st);
@@ -427,6 +401,8 @@ hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* p
     case 8: return fused_bj<T, 8>(c, g, omega, part1, part2, st);
     case 12: return fused_bj<T, 12>(c, g, omega, part1, part2, st);
     case 14: return fused_bj<T, 14>(c, g, omega, part1, part2, st);
+    case 22: return fused_bj<T, 22>(c, g, omega, part1, part2, st);
+    case 30: return fused_bj<T, 30>(c, g, omega, part1, part2, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -435,7 +411,7 @@ template <typename T>
 hipError_t launch_batch_fused(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
                               int parity, T omega, double* part1, double* part2, hipStream_t st)
 {
-    if (!fused_of(c) || c.kernel != HJ_KERNEL_MARCH || (c.vec != 1 && c.vec != 2) || c.ichunk < 1 || c.persistent)
+    if (!fused_of(c) || c.kernel != HJ_KERNEL_MARCH || !fused_bj_ok(c.vec, c.bj) || c.ichunk < 1 || c.persistent)
         return hipErrorInvalidValue;
     switch (c.bj) {
     case 2: return fused_batch_bj<T, 2>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
@@ -444,6 +420,8 @@ hipError_t launch_batch_fused(const hj_config& c, const Instance<T>* inst, const
     case 8: return fused_batch_bj<T, 8>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
     case 12: return fused_batch_bj<T, 12>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
     case 14: return fused_batch_bj<T, 14>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+    case 22: return fused_batch_bj<T, 22>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
+    case 30: return fused_batch_bj<T, 30>(c, inst, tile_inst, ntiles, parity, omega, part1, part2, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -16,9 +16,21 @@ inline int vec_of(const hj_config& c) { return c.kernel == HJ_KERNEL_DIRECT ? 1 
 
 inline bool fused_of(const hj_config& c) { return c.tsteps == 2; }
 
-// Own k cells per tile of the two-iteration kernels: a 64-lane row minus its
-// halo (vec 1), or a whole 64-lane row with a halo wave beside it (vec 2).
-inline int fused_tk(const hj_config& c) { return c.vec == 2 ? kWave : kWave - 2; }
+// Row layouts of the two-iteration kernels (hj_config::vec when tsteps is 2):
+// 1: one 64-lane row per wave, 62 own cells; 2: 64 own cells per row with a
+// halo wave beside the rows; 4: two 32-lane rows per wave, 30 own cells.
+// Own k cells per tile:
+inline int fused_tk(const hj_config& c) { return c.vec == 2 ? kWave : c.vec == 4 ? kWave / 2 - 2 : kWave - 2; }
+
+// The bj (own rows per tile) each layout is built for: the workgroup is
+// bj+2 waves (layout 1), bj+3 waves (layout 2) or (bj+2)/2 waves (layout 4).
+constexpr bool fused_bj_ok(int vec, int bj)
+{
+    return vec == 1   ? (bj == 2 || bj == 4 || bj == 6 || bj == 8 || bj == 14)
+           : vec == 2 ? (bj == 2 || bj == 4 || bj == 6 || bj == 8 || bj == 12)
+           : vec == 4 ? (bj == 6 || bj == 14 || bj == 22 || bj == 30)
+                      : false;
+}
 
 // LDS bytes per staged plane of the flat kernel.
 constexpr int kFlatPlaneBytesHost = 10240;

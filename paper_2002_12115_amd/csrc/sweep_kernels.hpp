@@ -384,9 +384,11 @@ __global__ __launch_bounds__(kWave * BJ) void direct_kernel(Grid<T> g, T omega, 
 
 // ---- fused kernel: two Jacobi iterations per pass over HBM -------------------
 //
-// A workgroup of BJ+2 waves owns a tile of BJ rows x 62 cells and marches
-// along i. Wave r, lane l sits on the extended cell (j0-1+r, k0-1+l), so the
-// waves together cover the tile plus a one-cell halo in j and k. At step i
+// A workgroup owns a tile of BJ rows x (W-2) cells and marches along i. Its
+// threads sit on the tile's extended cells, in rows of W lanes (W = 64: one
+// row per wave; W = 32: two rows per wave, so (BJ+2)/2 waves): thread t on
+// (j0-1 + t/W, k0-1 + t%W), so together they cover the tile plus a one-cell
+// halo in j and k. At step i
 // every thread computes the first iteration at its extended cell of plane i
 // (p1, from p0 planes i-1..i+1 staged in an LDS ring with a two-cell halo)
 // into a second LDS ring. After a barrier the tile's own cells compute the
@@ -397,16 +399,19 @@ __global__ __launch_bounds__(kWave * BJ) void direct_kernel(Grid<T> g, T omega, 
 // (overlapped tiling). Cells on the domain shell carry p0 unchanged into p1.
 // Each interior cell's first-iteration ss is summed by the workgroup that
 // owns it, so both iterations' gosa are exact partitions.
-template <typename T, int BJ>
+template <typename T, int BJ, int W>
 struct alignas(16) FusedLds {
-    static constexpr int XW = kWave;      // extended row: k0-1 .. k0+62
+    static_assert(W == kWave || W == kWave / 2, "rows of 64 or 32 lanes");
+    static_assert(((BJ + 2) * W) % kWave == 0, "whole waves");
+    static constexpr int XW = W;          // extended row: k0-1 .. k0+W-2
     static constexpr int TK = XW - 2;     // own cells per row
     static constexpr int R1 = BJ + 2;     // rows of p1 (j0-1 .. j0+BJ)
     static constexpr int R0 = BJ + 4;     // rows of p0 (j0-2 .. j0+BJ+1)
-    static constexpr int W0 = XW + 2;     // cols of p0 (k0-2 .. k0+63)
+    static constexpr int W0 = XW + 2;     // cols of p0 (k0-2 .. k0+W-1)
+    static constexpr int NW = R1 * W / kWave;   // waves
     T p0[4][R0][W0];
     T p1[4][R1][XW];
-    double red[BJ + 2];
+    double red[NW];
 };
 
 template <typename T>
@@ -414,59 +419,60 @@ struct P0Regs {
     T own, lo, hi, col;
 };
 
-// Fetch p0 plane ii for the tile: own extended cell, row j0-2 (wave 0),
-// row j0+BJ+1 (last wave) and columns k0-2 / k0+63 (threads < 2*(BJ+4)).
-template <typename T, int BJ>
+// Fetch p0 plane ii for the tile: own extended cell, row j0-2 (the first
+// row of threads), row j0+BJ+1 (the last row) and columns k0-2 / k0+W-1
+// (threads < 2*(BJ+4)).
+template <typename T, int BJ, int W>
 __device__ __forceinline__ void fused_fetch(const Grid<T>& g, int ii, int j0, int k0, P0Regs<T>& r)
 {
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int col = threadIdx.x % W, row = threadIdx.x / W;
     const T* base = g.src + (long long)ii * g.S;
-    const int k = k0 - 1 + lane, j = j0 - 1 + w;
+    const int k = k0 - 1 + col, j = j0 - 1 + row;
     if (j <= g.ny - 1 && k <= g.nz - 1) r.own = base[(long long)j * g.P + k];
-    if (w == 0 && j0 - 2 >= 0 && k <= g.nz - 1) r.lo = base[(long long)(j0 - 2) * g.P + k];
-    if (w == BJ + 1 && j0 + BJ + 1 <= g.ny - 1 && k <= g.nz - 1)
+    if (row == 0 && j0 - 2 >= 0 && k <= g.nz - 1) r.lo = base[(long long)(j0 - 2) * g.P + k];
+    if (row == BJ + 1 && j0 + BJ + 1 <= g.ny - 1 && k <= g.nz - 1)
         r.hi = base[(long long)(j0 + BJ + 1) * g.P + k];
     const int t = threadIdx.x;
     if (t < 2 * (BJ + 4)) {
         const int jj = j0 - 2 + (t >> 1);
-        const int kk = (t & 1) ? k0 + kWave - 1 : k0 - 2;
+        const int kk = (t & 1) ? k0 + W - 1 : k0 - 2;
         if (jj >= 0 && jj <= g.ny - 1 && kk >= 0 && kk <= g.nz - 1) r.col = base[(long long)jj * g.P + kk];
     }
 }
 
-template <typename T, int BJ>
-__device__ __forceinline__ void fused_put(const Grid<T>& g, T (*pl)[FusedLds<T, BJ>::W0], int j0, int k0,
+template <typename T, int BJ, int W>
+__device__ __forceinline__ void fused_put(const Grid<T>& g, T (*pl)[FusedLds<T, BJ, W>::W0], int j0, int k0,
                                           const P0Regs<T>& r)
 {
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int k = k0 - 1 + lane, j = j0 - 1 + w;
-    if (j <= g.ny - 1 && k <= g.nz - 1) pl[w + 1][lane + 1] = r.own;
-    if (w == 0 && j0 - 2 >= 0 && k <= g.nz - 1) pl[0][lane + 1] = r.lo;
-    if (w == BJ + 1 && j0 + BJ + 1 <= g.ny - 1 && k <= g.nz - 1) pl[BJ + 3][lane + 1] = r.hi;
+    const int col = threadIdx.x % W, row = threadIdx.x / W;
+    const int k = k0 - 1 + col, j = j0 - 1 + row;
+    if (j <= g.ny - 1 && k <= g.nz - 1) pl[row + 1][col + 1] = r.own;
+    if (row == 0 && j0 - 2 >= 0 && k <= g.nz - 1) pl[0][col + 1] = r.lo;
+    if (row == BJ + 1 && j0 + BJ + 1 <= g.ny - 1 && k <= g.nz - 1) pl[BJ + 3][col + 1] = r.hi;
     const int t = threadIdx.x;
     if (t < 2 * (BJ + 4)) {
         const int jj = j0 - 2 + (t >> 1);
-        const int kk = (t & 1) ? k0 + kWave - 1 : k0 - 2;
-        if (jj >= 0 && jj <= g.ny - 1 && kk >= 0 && kk <= g.nz - 1) pl[t >> 1][(t & 1) ? kWave + 1 : 0] = r.col;
+        const int kk = (t & 1) ? k0 + W - 1 : k0 - 2;
+        if (jj >= 0 && jj <= g.ny - 1 && kk >= 0 && kk <= g.nz - 1) pl[t >> 1][(t & 1) ? W + 1 : 0] = r.col;
     }
 }
 
 // KEEP: hold the own cell's coefficients in registers for the second
 // iteration; otherwise re-read them (they were read one step earlier, so the
 // read is served by L2 when the first read was not non-temporal).
-template <typename T, int BJ, bool NT, bool KEEP>
+template <typename T, int BJ, int W, bool NT, bool KEEP>
 __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, int jt, int ib, int ie,
-                                           FusedLds<T, BJ>& sm, double& acc1, double& acc2)
+                                           FusedLds<T, BJ, W>& sm, double& acc1, double& acc2)
 {
-    constexpr int TK = FusedLds<T, BJ>::TK;
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    constexpr int TK = FusedLds<T, BJ, W>::TK;
+    const int col = threadIdx.x % W, row = threadIdx.x / W;
     const int k0 = 1 + kt * TK, j0 = 1 + jt * BJ;
-    const int k = k0 - 1 + lane, j = j0 - 1 + w;               // this thread's extended cell
+    const int k = k0 - 1 + col, j = j0 - 1 + row;              // this thread's extended cell
     const bool in_dom = (j <= g.ny - 1) && (k <= g.nz - 1);
     const bool jk_int = in_dom && j >= 1 && j <= g.ny - 2 && k >= 1 && k <= g.nz - 2;
-    const bool own = (w >= 1 && w <= BJ && lane >= 1 && lane <= TK);
+    const bool own = (row >= 1 && row <= BJ && col >= 1 && col <= TK);
     const bool out = own && jk_int;                             // an output cell of this tile
-    const int rho = w + 1, c = lane + 1;                        // position in the p0 tile
+    const int rho = row + 1, c = col + 1;                       // position in the p0 tile
     const long long rowoff = (long long)j * g.P + k;
 
     // p0 planes ib-2 .. ib (clipped at the shell)
@@ -474,8 +480,8 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
     P0Regs<T> rr;
     for (int ii = i_lo - 1; ii <= i_lo + 1; ++ii) {
         if (ii < 0) continue;
-        fused_fetch<T, BJ>(g, ii, j0, k0, rr);
-        fused_put<T, BJ>(g, sm.p0[ii & 3], j0, k0, rr);
+        fused_fetch<T, BJ, W>(g, ii, j0, k0, rr);
+        fused_put<T, BJ, W>(g, sm.p0[ii & 3], j0, k0, rr);
     }
     __syncthreads();
 
@@ -492,7 +498,7 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
     }
     for (int i = i_lo; i <= i_hi; ++i) {
         const bool more = (i + 2 <= i_hi + 1) && (i + 2 <= g.nx - 1);
-        if (more) fused_fetch<T, BJ>(g, i + 2, j0, k0, rr);
+        if (more) fused_fetch<T, BJ, W>(g, i + 2, j0, k0, rr);
         T nxt[NCOEF];
         if (jk_int && i + 1 <= i_hi && i + 1 <= g.nx - 2) {
             const long long o = (long long)(i + 1) * g.S + rowoff;
@@ -525,9 +531,9 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
             } else {
                 p1v = Pc[rho][c];                              // the shell is never updated
             }
-            sm.p1[i & 3][w][lane] = p1v;
+            sm.p1[i & 3][row][col] = p1v;
         }
-        if (more) fused_put<T, BJ>(g, sm.p0[(i + 2) & 3], j0, k0, rr);
+        if (more) fused_put<T, BJ, W>(g, sm.p0[(i + 2) & 3], j0, k0, rr);
         __syncthreads();
 
         // ---- second iteration at plane i-1, own cells
@@ -536,7 +542,7 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
             auto* Qm = sm.p1[(i2 - 1) & 3];
             auto* Qc = sm.p1[i2 & 3];
             auto* Qp = sm.p1[(i2 + 1) & 3];
-            const T qc = Qc[w][lane];
+            const T qc = Qc[row][col];
             T kc[NCOEF];
             if constexpr (KEEP) {
 #pragma unroll
@@ -548,12 +554,12 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
             }
             const T ss = cell_ss<T>(kc[CA0], kc[CA1], kc[CA2], kc[CA3], kc[CB0], kc[CB1], kc[CB2],
                                     kc[CC0], kc[CC1], kc[CC2], kc[CBND], kc[CWRK1],
-                                    Qp[w][lane], Qc[w + 1][lane], Qc[w][lane + 1],
-                                    bracket(Qp[w + 1][lane], Qp[w - 1][lane], Qm[w + 1][lane], Qm[w - 1][lane]),
-                                    bracket(Qc[w + 1][lane + 1], Qc[w - 1][lane + 1], Qc[w + 1][lane - 1],
-                                            Qc[w - 1][lane - 1]),
-                                    bracket(Qp[w][lane + 1], Qm[w][lane + 1], Qp[w][lane - 1], Qm[w][lane - 1]),
-                                    Qm[w][lane], Qc[w - 1][lane], Qc[w][lane - 1], qc);
+                                    Qp[row][col], Qc[row + 1][col], Qc[row][col + 1],
+                                    bracket(Qp[row + 1][col], Qp[row - 1][col], Qm[row + 1][col], Qm[row - 1][col]),
+                                    bracket(Qc[row + 1][col + 1], Qc[row - 1][col + 1], Qc[row + 1][col - 1],
+                                            Qc[row - 1][col - 1]),
+                                    bracket(Qp[row][col + 1], Qm[row][col + 1], Qp[row][col - 1], Qm[row][col - 1]),
+                                    Qm[row][col], Qc[row - 1][col], Qc[row][col - 1], qc);
             const T outv = qc + omega * ss;
             T* dst = g.dst + (long long)i2 * g.S + rowoff;
             if constexpr (NT) __builtin_nontemporal_store(outv, dst);
@@ -574,46 +580,54 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
 
 // One workgroup's whole share of a two-iteration pass: tile (kt, jt), i-chunk
 // ic, both iterations' gosa partials to slot L of part1 / part2.
-template <typename T, int BJ, bool NT, bool KEEP>
+template <typename T, int BJ, int W, bool NT, bool KEEP>
 __device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, int jt, int ic, int ichunk, int L,
-                                            FusedLds<T, BJ>& sm, double* __restrict__ part1,
+                                            FusedLds<T, BJ, W>& sm, double* __restrict__ part1,
                                             double* __restrict__ part2)
 {
     const int ib = 1 + ic * ichunk;
     int ie = ib + ichunk;
     if (ie > g.nx - 1) ie = g.nx - 1;
     double acc1 = 0.0, acc2 = 0.0;
-    fused_tile<T, BJ, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
-    acc1 = block_sum<BJ + 2>(acc1, sm.red);
+    fused_tile<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
+    constexpr int NW = FusedLds<T, BJ, W>::NW;
+    acc1 = block_sum<NW>(acc1, sm.red);
     if (threadIdx.x == 0) part1[L] = acc1;
-    acc2 = block_sum<BJ + 2>(acc2, sm.red);
+    acc2 = block_sum<NW>(acc2, sm.red);
     if (threadIdx.x == 0) part2[L] = acc2;
 }
 
-// bj 6 asks for four waves per SIMD, so that two of its 8-wave workgroups
-// share a CU (it then holds 128 VGPRs and spills a few).
-template <typename T, int BJ, bool NT, bool KEEP>
-__global__ __launch_bounds__(kWave * (BJ + 2)) __attribute__((amdgpu_waves_per_eu(BJ == 6 ? 4 : 1))) void fused_kernel(
+// Threads per workgroup of the two-iteration kernel with W-lane rows.
+template <int BJ, int W>
+constexpr int fused_threads() { return (BJ + 2) * W; }
+
+// bj 6 with 64-lane rows asks for four waves per SIMD, so that two of its
+// 8-wave workgroups share a CU (it then holds 128 VGPRs and spills a few).
+template <int BJ, int W>
+constexpr int fused_min_waves() { return (BJ == 6 && W == kWave) ? 4 : 1; }
+
+template <typename T, int BJ, int W, bool NT, bool KEEP>
+__global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fused_min_waves<BJ, W>()))) void fused_kernel(
     Grid<T> g, T omega, int ichunk, int kt_n, int jt_n, int remap, double* __restrict__ part1,
     double* __restrict__ part2)
 {
-    __shared__ FusedLds<T, BJ> sm;
+    __shared__ FusedLds<T, BJ, W> sm;
     const int L = remap_xcd(blockIdx.x, gridDim.x, remap);
     const int kt = L % kt_n;
     const int jt = (L / kt_n) % jt_n;
     const int ic = L / (kt_n * jt_n);
-    fused_block<T, BJ, NT, KEEP>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
+    fused_block<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
 }
 
 // Two iterations over every instance of a batch: one workgroup per tile of
 // the flattened list (instance descriptors as for batch_kernel, with the
 // two-iteration tile counts), gridDim.x == the number of tiles.
-template <typename T, int BJ, bool NT, bool KEEP>
-__global__ __launch_bounds__(kWave * (BJ + 2)) __attribute__((amdgpu_waves_per_eu(BJ == 6 ? 4 : 1))) void fused_batch_kernel(
+template <typename T, int BJ, int W, bool NT, bool KEEP>
+__global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fused_min_waves<BJ, W>()))) void fused_batch_kernel(
     const Instance<T>* __restrict__ inst, const int* __restrict__ tile_inst, int parity, T omega, int remap,
     double* __restrict__ part1, double* __restrict__ part2)
 {
-    __shared__ FusedLds<T, BJ> sm;
+    __shared__ FusedLds<T, BJ, W> sm;
     const int L = remap_xcd(blockIdx.x, gridDim.x, remap);
     const Instance<T>& d = inst[tile_inst[L]];
     Grid<T> g;
@@ -626,7 +640,7 @@ __global__ __launch_bounds__(kWave * (BJ + 2)) __attribute__((amdgpu_waves_per_e
     const int kt = t % d.kt_n;
     const int jt = (t / d.kt_n) % d.jt_n;
     const int ic = t / (d.kt_n * d.jt_n);
-    fused_block<T, BJ, NT, KEEP>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
+    fused_block<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
 }
 
 // ---- wide fused kernel: 64 own cells per row and a halo wave -----------------

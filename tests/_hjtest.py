@@ -93,6 +93,9 @@ def fused_configs():
     for bj in (2, 4, 6, 8, 12):          # 64-cell rows with a halo wave
         for ich, nt, rm, rr in ((1, 0, 1, 0), (3, 1, 0, 1), (1000, 0, 1, 1)):
             out.append(cfg(bj=bj, vec=2, ichunk=ich, nontemporal=nt, xcd_remap=rm, tsteps=2, reread=rr))
+    for bj in (6, 14, 22, 30):           # two 30-cell rows per wave
+        for ich, nt, rm, rr in ((1, 1, 1, 0), (4, 0, 0, 1), (1000, 0, 1, 0)):
+            out.append(cfg(bj=bj, vec=4, ichunk=ich, nontemporal=nt, xcd_remap=rm, tsteps=2, reread=rr))
     return out
 
 
@@ -110,5 +113,5 @@ def f32_configs():
 def cfg_id(c):
     d = c.as_dict()
     k = ("direct" if d["kernel"] == 0 else "flat" if d["kernel"] == 2 else
-         ("wide%d" if d["vec"] == 2 else "fused%d") % d["reread"] if d["tsteps"] == 2 else "march")
+         ({1: "fused%d", 2: "wide%d", 4: "narrow%d"}[d["vec"]]) % d["reread"] if d["tsteps"] == 2 else "march")
     return "%s-bj%d-v%d-ic%d-nt%d-rm%d" % (k, d["bj"], d["vec"], d["ichunk"], d["nontemporal"], d["xcd_remap"])

@@ -175,6 +175,7 @@ def test_gene_decoding(lib):
                     if d["tsteps"] == 2:                # two-iteration batches: renumbering, no persistent grid
                         assert d["kernel"] == 1 and d["persistent"] == 0 and d["ichunk"] == 4 << ((g >> 5) & 7)
                         assert d["xcd_remap"] == (g >> 9) & 1
+                        assert d["vec"] == (4 if (g >> 4) & 1 else 1)   # batches: narrow rows on bit 4
                     else:
                         assert d["tsteps"] == 1 and d["xcd_remap"] == 0
     # folded codes: vec code 2 is 1 for FP64 and 4 for FP32; direct reads bj 1 as 2
@@ -189,6 +190,8 @@ def test_gene_decoding(lib):
     assert dec(0, 1 | (1 << 10) | (2 << 3))["reread"] == 0
     assert [dec(0, 1 | (1 << 10) | (b << 1))["bj"] for b in range(4)] == [14, 6, 4, 8]
     assert [dec(0, 1 | (1 << 10) | (2 << 3) | (b << 1))["bj"] for b in range(4)] == [12, 6, 4, 8]
+    assert [dec(1, 1 | (1 << 10) | (2 << 3) | (b << 1), batch=1, shape=(0, 0, 0))["bj"]
+            for b in range(4)] == [14, 6, 22, 30]
     # the 64-cell rows tile a 256-wide interior in 4: the chunks fit 256 workgroups in 4 x 16 x 4
     assert dec(0, 1 | (1 << 10) | (2 << 3) | (3 << 1))["ichunk"] == 32
     # their chunks: the longest within 256, 512, ... workgroups (5 x 16 tiles of bj 8 here)

@@ -38,6 +38,10 @@ def batch_configs(dtype):
         for ich, rr, rm in ((1, 1, 1), (7, 0, 0), (64, 1, 0)):
             out.append(hj.Config.make(kernel=1, bj=bj, vec=2, ichunk=ich, nontemporal=0, use_graph=1,
                                       xcd_remap=rm, persistent=0, tsteps=2, reread=rr))
+    for bj in (6, 14, 22, 30):                  # two iterations, two 30-cell rows per wave
+        for ich, rr, rm in ((1, 0, 1), (9, 1, 0)):
+            out.append(hj.Config.make(kernel=1, bj=bj, vec=4, ichunk=ich, nontemporal=0, use_graph=1,
+                                      xcd_remap=rm, persistent=0, tsteps=2, reread=rr))
     return out
 
 

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 @st.composite
 def configs(draw, dtype):
-    kind = draw(st.sampled_from(["direct", "march", "fused", "wide"]))
+    kind = draw(st.sampled_from(["direct", "march", "fused", "wide", "narrow"]))
     nt = draw(st.integers(0, 1))
     rm = draw(st.integers(0, 1))
     if kind == "direct":
@@ -23,6 +23,9 @@ def configs(draw, dtype):
         vecs = [1, 2] if dtype == "f64" else [1, 2, 4]
         return cfg(bj=draw(st.sampled_from([1, 2, 4, 8])), vec=draw(st.sampled_from(vecs)),
                    ichunk=draw(st.integers(1, 40)), nontemporal=nt, xcd_remap=rm)
+    if kind == "narrow":
+        return cfg(bj=draw(st.sampled_from([6, 14, 22, 30])), vec=4, ichunk=draw(st.integers(1, 40)),
+                   nontemporal=nt, xcd_remap=rm, tsteps=2, reread=draw(st.integers(0, 1)))
     if kind == "wide":
         return cfg(bj=draw(st.sampled_from([2, 4, 6, 8, 12])), vec=2, ichunk=draw(st.integers(1, 40)),
                    nontemporal=nt, xcd_remap=rm, tsteps=2, reread=draw(st.integers(0, 1)))
