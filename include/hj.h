@@ -147,6 +147,11 @@ int hj_sweep_async(hj_solver h, int n_iter, double omega, double* dev_gosa_hist)
 /* gosa of the current field, without updating it. Synchronous. */
 int hj_residual(hj_solver h, double* gosa);
 
+/* The configuration the next sweep runs with: the library default, the
+ * tuning cache's entry for this problem, the last autotune winner or the
+ * last hj_set_config. hj_set_config returns HJ_ERR_ARG for a configuration
+ * the library does not build (see hj_config) or a flat kernel that does not
+ * fit the grid, and leaves the previous one in place. */
 int hj_get_config(hj_solver h, hj_config* out);
 int hj_set_config(hj_solver h, const hj_config* cfg);
 
@@ -165,11 +170,10 @@ int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double*
 
 /* The paper's genetic search (sections 4 and 5.1.2) as the search strategy
  * of the autotuner, instead of trying every candidate. A gene is 11 bits and
- * every value names a configuration (hj_gene_config): bit 0 kernel, bits 1-2
- * bj, bits 3-4 vec, bits 5-7 one of eight i-chunk lengths, bit 8
- * non-temporal, bit 9 XCD renumbering, bit 10 two iterations per pass. population and generations individuals are measured as
- * by hj_autotune (same parity gate) with fitness (time)^(-1/2); a failed
- * measurement or a gene that names no configuration counts as 1000 s.
+ * every value names a configuration (hj_gene_config gives the bits).
+ * population x generations individuals are measured as by hj_autotune (same
+ * parity gate) with fitness (time)^(-1/2); a failed measurement or a gene
+ * that names no configuration counts as 1000 s.
  * Roulette selection with elitism, one-point crossover with probability pc,
  * per-bit mutation with probability pm (the paper uses 0.9 and 0.05, and a
  * population and generation count no larger than the gene length). Random
@@ -213,35 +217,54 @@ int hj_sync(hj_solver h);
 /* The HIP stream used by the handle (a hipStream_t). */
 int hj_get_stream(hj_solver h, void** stream);
 
+/* Wait for the handle's queued work, then release it: its device memory
+ * when it owns it (hj_create), its library-created stream, and the handle
+ * itself, which is invalid afterwards (HJ_ERR_HANDLE). */
 int hj_destroy(hj_solver h);
 
 /* ---- batch of independent solves ---------------------------------------- */
 
-/* n solves of individual shapes, all in one device slab, advanced together:
+/* n >= 1 independent solves (the same operator, each with its own shape
+ * nx[t] x ny[t] x nz[t], every side >= 3, else HJ_ERR_SHAPE naming the
+ * instance) held in one device slab the batch owns, and advanced together:
  * each pass is one launch over a flattened list of every instance's tiles
  * (one iteration, or two with tsteps 2, where an odd remainder runs one
- * one-iteration pass), and the loop is replayed as a captured HIP graph. */
+ * one-iteration pass), and the loop is replayed as a captured HIP graph.
+ * The shape arrays are read during the call only. stream as for hj_create. */
 int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* ny,
                     const int* nz, void* stream);
+
+/* Upload / download one field of instance inst (0 <= inst < n) as hj_upload
+ * / hj_upload_f64 / hj_download do for a single solve (dense host array of
+ * that instance's shape; HJ_P also resets the partner; HJ_WRK2 cannot be
+ * uploaded). Synchronous. */
 int hj_batch_upload(hj_batch b, int inst, int field, const void* host_src);
 int hj_batch_upload_f64(hj_batch b, int inst, int field, const double* host_src);
 int hj_batch_download(hj_batch b, int inst, int field, void* host_dst);
 
-/* gosa_last (nullable, n doubles), gosa_hist (nullable, n_iter*n doubles,
- * [iteration][instance]). */
+/* n_iter iterations of every instance (HJ_ERR_STATE until every input field
+ * of every instance is uploaded). gosa_last (nullable, n doubles),
+ * gosa_hist (nullable, n_iter*n doubles, [iteration][instance]), each
+ * instance's sum in a fixed order. Synchronous. */
 int hj_batch_sweep(hj_batch b, int n_iter, double omega, double* gosa_last, double* gosa_hist);
+
+/* gosa of every instance's current field (n doubles), no update. */
 int hj_batch_residual(hj_batch b, double* gosa);
 int hj_batch_get_config(hj_batch b, hj_config* out);
 /* Any supported configuration but the direct kernel; a flat kernel must fit
  * every instance (else HJ_ERR_ARG). xcd_remap and reread are kept for
  * two-iteration passes (tsteps 2, not persistent) and cleared otherwise. */
 int hj_batch_set_config(hj_batch b, const hj_config* cfg);
+/* As hj_autotune, over the batch's candidates (one configuration for all
+ * instances); the parity gate compares every instance's current field, and
+ * the cache line is keyed by a hash of the instance shapes. */
 int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, double* best_ms);
 /* Genetic search over the batch's configuration (as hj_autotune_ga, with
  * the batch reading of the gene that hj_gene_config documents). */
 int hj_batch_autotune_ga(hj_batch b, int population, int generations, unsigned long long seed, double pc,
                          double pm, int n_sweeps, int repeats, hj_config* best, double* best_ms,
                          int* evaluations);
+/* As hj_destroy: waits, then frees the slab and the handle. */
 int hj_batch_destroy(hj_batch b);
 
 /* ---- diagnostics ---------------------------------------------------------- */
