@@ -18,6 +18,7 @@
 #include <exception>
 #include <functional>
 #include <mutex>
+#include <shared_mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -182,6 +183,62 @@ hj_config reference_config(int dtype)
     return c;
 }
 
+// ---- runtime calls that must not overlap a graph capture ----------------------
+//
+// A HIP graph capture on one thread is invalidated by a runtime call on any
+// thread that allocates, frees or creates/destroys streams and graphs. The
+// library's own such calls take this lock exclusively; captures take it
+// shared, so captures may overlap each other but never those calls.
+std::shared_mutex g_capture_mu;
+using RuntimeLock = std::unique_lock<std::shared_mutex>;
+
+void dev_alloc(void** p, size_t n)
+{
+    RuntimeLock lk(g_capture_mu);
+    HIPCHK(hipMalloc(p, n));
+}
+void dev_free(void* p)
+{
+    RuntimeLock lk(g_capture_mu);
+    (void)hipFree(p);
+}
+void host_alloc(void** p, size_t n)
+{
+    RuntimeLock lk(g_capture_mu);
+    HIPCHK(hipHostMalloc(p, n, hipHostMallocDefault));
+}
+void host_free(void* p)
+{
+    RuntimeLock lk(g_capture_mu);
+    (void)hipHostFree(p);
+}
+void stream_create(hipStream_t* s)
+{
+    RuntimeLock lk(g_capture_mu);
+    HIPCHK(hipStreamCreateWithFlags(s, hipStreamNonBlocking));
+}
+void stream_destroy(hipStream_t s)
+{
+    RuntimeLock lk(g_capture_mu);
+    (void)hipStreamDestroy(s);
+}
+void exec_destroy(hipGraphExec_t g)
+{
+    RuntimeLock lk(g_capture_mu);
+    (void)hipGraphExecDestroy(g);
+}
+
+// Errors that mean a capture was disturbed from outside (another thread's
+// runtime call); the work can still run eagerly.
+bool capture_disturbed(hipError_t e)
+{
+    return e == hipErrorStreamCaptureInvalidated || e == hipErrorStreamCaptureImplicit ||
+           e == hipErrorStreamCaptureUnsupported || e == hipErrorStreamCaptureIsolation ||
+           e == hipErrorStreamCaptureMerge || e == hipErrorStreamCaptureUnjoined ||
+           e == hipErrorStreamCaptureUnmatched || e == hipErrorStreamCaptureWrongThread ||
+           e == hipErrorCapturedEvent;
+}
+
 // ---- device buffers -----------------------------------------------------------
 
 struct DevBuf {
@@ -191,12 +248,12 @@ struct DevBuf {
     {
         if (need <= bytes) return;
         release();
-        HIPCHK(hipMalloc(&p, need));
+        dev_alloc(&p, need);
         bytes = need;
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p);
         p = nullptr;
         bytes = 0;
     }
@@ -209,12 +266,12 @@ struct PinBuf {
     {
         if (need <= bytes) return;
         release();
-        HIPCHK(hipHostMalloc(&p, need, hipHostMallocDefault));
+        host_alloc(&p, need);
         bytes = need;
     }
     void release()
     {
-        if (p) (void)hipHostFree(p);
+        if (p) host_free(p);
         p = nullptr;
         bytes = 0;
     }
@@ -258,14 +315,14 @@ struct GraphCache {
     void add(const GraphEntry& e)
     {
         if (v.size() >= 8) {
-            (void)hipGraphExecDestroy(v.front().exec);
+            exec_destroy(v.front().exec);
             v.erase(v.begin());
         }
         v.push_back(e);
     }
     void clear()
     {
-        for (auto& e : v) (void)hipGraphExecDestroy(e.exec);
+        for (auto& e : v) exec_destroy(e.exec);
         v.clear();
     }
 };
@@ -273,6 +330,7 @@ struct GraphCache {
 template <typename Enq>
 hipGraphExec_t capture(hipStream_t cap, Enq&& enqueue)
 {
+    std::shared_lock<std::shared_mutex> lk(g_capture_mu);
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     try {
@@ -289,6 +347,26 @@ hipGraphExec_t capture(hipStream_t cap, Enq&& enqueue)
     (void)hipGraphDestroy(graph);
     HIPCHK(e);
     return exec;
+}
+
+// The graph of an n_iter loop from parity `parity`: from the cache, or
+// captured and cached. nullptr when the capture was disturbed from outside
+// (the caller then enqueues the same work eagerly; nothing ran on the device).
+template <typename Enq>
+hipGraphExec_t find_or_capture(GraphCache& graphs, hipStream_t cap, int n_iter, double omega, int parity,
+                               const hj_config& cfg, double* out, Enq&& enqueue)
+{
+    if (hipGraphExec_t ex = graphs.find(n_iter, omega, parity, cfg, out)) return ex;
+    hipGraphExec_t ex = nullptr;
+    try {
+        ex = capture(cap, [&](hipStream_t s) { enqueue(parity, s); });
+    } catch (const HipFail& f) {
+        if (!capture_disturbed(f.e)) throw;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    graphs.add(GraphEntry{n_iter, bits_of(omega), parity, cfg, out, ex});
+    return ex;
 }
 
 std::mutex g_reg_mu;
@@ -708,13 +786,12 @@ struct hj_solver_s {
     // Enqueue the whole loop on `stream`, as a graph replay when configured.
     void run(int n_iter, double omega, double* out)
     {
-        if (cfg.use_graph) {
-            hipGraphExec_t ex = graphs.find(n_iter, omega, parity, cfg, out);
-            if (!ex) {
-                const int par = parity;
-                ex = capture(cap, [&](hipStream_t s) { enqueue(n_iter, omega, par, out, s); });
-                graphs.add(GraphEntry{n_iter, bits_of(omega), parity, cfg, out, ex});
-            }
+        hipGraphExec_t ex = cfg.use_graph ? find_or_capture(graphs, cap, n_iter, omega, parity, cfg, out,
+                                                            [&](int par, hipStream_t s) {
+                                                                enqueue(n_iter, omega, par, out, s);
+                                                            })
+                                          : nullptr;
+        if (ex) {
             HIPCHK(hipGraphLaunch(ex, stream));
             parity ^= (launches(n_iter) & 1);
         } else {
@@ -755,22 +832,22 @@ int solver_init(hj_solver* out, int dtype, int nx, int ny, int nz, void* dev_sla
         if (dev_slab) {
             h->slab = static_cast<char*>(dev_slab);
         } else {
-            HIPCHK(hipMalloc(reinterpret_cast<void**>(&h->slab), L.slab_bytes));
+            dev_alloc(reinterpret_cast<void**>(&h->slab), L.slab_bytes);
             h->owns_slab = true;
         }
         if (stream) {
             h->stream = static_cast<hipStream_t>(stream);
         } else {
-            HIPCHK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+            stream_create(&h->stream);
             h->owns_stream = true;
         }
-        HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        stream_create(&h->cap);
         HIPCHK(hipEventCreate(&h->ev0));
         HIPCHK(hipEventCreate(&h->ev1));
     } catch (...) {
-        if (h->owns_slab && h->slab) (void)hipFree(h->slab);
-        if (h->owns_stream && h->stream) (void)hipStreamDestroy(h->stream);
-        if (h->cap) (void)hipStreamDestroy(h->cap);
+        if (h->owns_slab && h->slab) dev_free(h->slab);
+        if (h->owns_stream && h->stream) stream_destroy(h->stream);
+        if (h->cap) stream_destroy(h->cap);
         if (h->ev0) (void)hipEventDestroy(h->ev0);
         if (h->ev1) (void)hipEventDestroy(h->ev1);
         delete h;
@@ -794,7 +871,7 @@ struct Stager {
     void ensure()
     {
         for (int q = 0; q < 2; ++q) {
-            if (!buf[q]) HIPCHK(hipHostMalloc(&buf[q], kBytes, hipHostMallocDefault));
+            if (!buf[q]) host_alloc(&buf[q], kBytes);
             if (!ev[q]) HIPCHK(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
         }
     }
@@ -1347,9 +1424,9 @@ int hj_destroy(hj_solver h)
     h->part.release();
     h->gosa.release();
     h->host_gosa.release();
-    if (h->owns_slab) (void)hipFree(h->slab);
-    if (h->owns_stream) (void)hipStreamDestroy(h->stream);
-    (void)hipStreamDestroy(h->cap);
+    if (h->owns_slab) dev_free(h->slab);
+    if (h->owns_stream) stream_destroy(h->stream);
+    stream_destroy(h->cap);
     (void)hipEventDestroy(h->ev0);
     (void)hipEventDestroy(h->ev1);
     h->magic = 0;
@@ -1508,9 +1585,13 @@ struct hj_batch_s {
         out.d_inst.ensure(sizeof(Instance<T>) * std::max(n, 1));
         out.d_tile_inst.ensure(sizeof(int) * std::max(out.ntiles, 1));
         out.d_seg.ensure(sizeof(int) * (n + 1));
-        HIPCHK(hipMemcpy(out.d_inst.p, inst.data(), sizeof(Instance<T>) * n, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(out.d_tile_inst.p, tile_inst.data(), sizeof(int) * out.ntiles, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(out.d_seg.p, seg.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice));
+        // on the batch's own stream (a copy on the legacy stream would disturb
+        // graph captures running on other threads)
+        HIPCHK(hipMemcpyAsync(out.d_inst.p, inst.data(), sizeof(Instance<T>) * n, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(out.d_tile_inst.p, tile_inst.data(), sizeof(int) * out.ntiles, hipMemcpyHostToDevice,
+                              stream));
+        HIPCHK(hipMemcpyAsync(out.d_seg.p, seg.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));
         if (c.persistent) {
             const int occ = batch_occupancy<T>(c);
             out.grid = std::max(1, std::min(out.ntiles, std::max(occ, 1) * cus));
@@ -1622,13 +1703,12 @@ struct hj_batch_s {
 
     void run(int n_iter, double omega, double* out)
     {
-        if (cfg.use_graph) {
-            hipGraphExec_t ex = graphs.find(n_iter, omega, parity, cfg, out);
-            if (!ex) {
-                const int par = parity;
-                ex = capture(cap, [&](hipStream_t s) { enqueue(n_iter, omega, par, out, s); });
-                graphs.add(GraphEntry{n_iter, bits_of(omega), parity, cfg, out, ex});
-            }
+        hipGraphExec_t ex = cfg.use_graph ? find_or_capture(graphs, cap, n_iter, omega, parity, cfg, out,
+                                                            [&](int par, hipStream_t s) {
+                                                                enqueue(n_iter, omega, par, out, s);
+                                                            })
+                                          : nullptr;
+        if (ex) {
             HIPCHK(hipGraphLaunch(ex, stream));
             parity ^= (launches(n_iter) & 1);
         } else {
@@ -1710,23 +1790,23 @@ int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* n
             }
         }
         try {
-            HIPCHK(hipMalloc(reinterpret_cast<void**>(&b->slab), total));
+            dev_alloc(reinterpret_cast<void**>(&b->slab), total);
             if (stream) {
                 b->stream = static_cast<hipStream_t>(stream);
             } else {
-                HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+                stream_create(&b->stream);
                 b->owns_stream = true;
             }
-            HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+            stream_create(&b->cap);
             HIPCHK(hipEventCreate(&b->ev0));
             HIPCHK(hipEventCreate(&b->ev1));
             int dev = 0;
             HIPCHK(hipGetDevice(&dev));
             HIPCHK(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev));
         } catch (...) {
-            if (b->slab) (void)hipFree(b->slab);
-            if (b->owns_stream && b->stream) (void)hipStreamDestroy(b->stream);
-            if (b->cap) (void)hipStreamDestroy(b->cap);
+            if (b->slab) dev_free(b->slab);
+            if (b->owns_stream && b->stream) stream_destroy(b->stream);
+            if (b->cap) stream_destroy(b->cap);
             if (b->ev0) (void)hipEventDestroy(b->ev0);
             if (b->ev1) (void)hipEventDestroy(b->ev1);
             delete b;
@@ -2061,9 +2141,9 @@ int hj_batch_destroy(hj_batch b)
     b->host_gosa.release();
     b->tl.release();
     b->tl1.release();
-    (void)hipFree(b->slab);
-    if (b->owns_stream) (void)hipStreamDestroy(b->stream);
-    (void)hipStreamDestroy(b->cap);
+    dev_free(b->slab);
+    if (b->owns_stream) stream_destroy(b->stream);
+    stream_destroy(b->cap);
     (void)hipEventDestroy(b->ev0);
     (void)hipEventDestroy(b->ev1);
     b->magic = 0;
