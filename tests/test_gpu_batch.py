@@ -119,6 +119,32 @@ def test_two_iteration_batch_odd_counts_and_residual(dtype):
             assert field_err(outs[t], pref) <= F32_FIELD_RTOL, (t, shapes[t])
 
 
+@pytest.mark.parametrize("tsteps", [1, 2])
+def test_batch_graph_replays_match_eager(tsteps):
+    shapes, seeds = inputs.batch_shapes(5, 5, lo_xy=5, hi_xy=30, lo_z=5, hi_z=100)
+    arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
+    extra = dict(bj=6, vec=1, ichunk=5, xcd_remap=1, tsteps=2) if tsteps == 2 else dict(bj=4, vec=1, ichunk=4)
+    res = {}
+    for graph in (0, 1):
+        say("batch graph", graph, tsteps)
+        with hj.Batch("f64", shapes) as b:
+            b.config = hj.Config.make(**dict(b.config.as_dict(), use_graph=graph, **extra))
+            for t, a in enumerate(arrays):
+                b.upload_all(t, a)
+            hs, ps = [], []
+            for rep in range(4):
+                b.sweep(5, 0.8)
+                hs.append(b.gosa_history.copy())
+                ps.append([b.download(t) for t in range(len(shapes))])
+                _ = b.residual()
+            res[graph] = (hs, ps)
+    for a, c in zip(res[0][0], res[1][0]):
+        assert np.array_equal(a, c)
+    for a, c in zip(res[0][1], res[1][1]):
+        for x, y in zip(a, c):
+            assert np.array_equal(x, y)
+
+
 def test_batch_autotune_keeps_parity():
     shapes, seeds = small_batch(1, 5)
     arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]

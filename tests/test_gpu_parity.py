@@ -117,14 +117,24 @@ def test_residual_matches_oracle_and_history():
             assert s.gosa_history[0] == pytest.approx(g4, rel=1e-12)
 
 
-def test_graph_replays_match_eager():
+GRAPH_CONFIGS = [None,
+                 dict(kernel=1, bj=8, vec=2, ichunk=7, nontemporal=0, xcd_remap=1, tsteps=2, reread=0),
+                 dict(kernel=1, bj=14, vec=4, ichunk=9, nontemporal=0, xcd_remap=1, tsteps=2, reread=1)]
+
+
+@pytest.mark.parametrize("extra", GRAPH_CONFIGS, ids=["default", "wide", "narrow"])
+def test_graph_replays_match_eager(extra):
+    """Replays of captured loops (two cached graphs alternate when a call has
+    an odd number of passes) equal eager launches, with host work between."""
     shape = (30, 33, 100)
     f = inputs.fields(2002, shape)
     for dtype in ("f64", "f32"):
         res = {}
         for graph in (0, 1):
-            say("graph", graph, dtype)
+            say("graph", graph, dtype, extra)
             with hj.Solver(dtype, shape) as s:
+                if extra:
+                    s.set(**extra)
                 s.set(use_graph=graph)
                 s.upload_all(f)
                 hs, ps = [], []
