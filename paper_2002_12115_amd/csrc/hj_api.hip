@@ -1818,6 +1818,8 @@ int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* n
     });
 }
 
+}  // extern "C"
+
 namespace {
 
 int batch_upload(hj_batch b, int inst, int field, const void* src, bool src_f64)
@@ -1842,6 +1844,8 @@ int batch_upload(hj_batch b, int inst, int field, const void* src, bool src_f64)
 }
 
 }  // namespace
+
+extern "C" {
 
 int hj_batch_upload(hj_batch b, int inst, int field, const void* src)
 {
@@ -1933,6 +1937,8 @@ int hj_batch_set_config(hj_batch b, const hj_config* cfg)
         return HJ_OK;
     });
 }
+
+}  // extern "C"
 
 namespace {
 
@@ -2045,6 +2051,8 @@ std::vector<hj_config> batch_candidates(const hj_batch_s* b)
 }
 
 }  // namespace
+
+extern "C" {
 
 int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, double* best_ms)
 {
