@@ -215,12 +215,14 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
         s.sweep(w.iters, w.omega)
     torch.cuda.synchronize()
     kernel_ms = 0.0
+    step_ms = []
     t0 = time.perf_counter()
     for _ in range(steps):
         s.sweep(w.iters, w.omega)
-        kernel_ms += s.last_ms          # HIP events on the solver's stream around each solve
+        step_ms.append(s.last_ms)       # HIP events on the solver's stream around each solve
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    kernel_ms = sum(step_ms)
     updates = n_int * w.iters * steps
     glups = updates / wall / 1e9
     # Algorithmic bytes: 13 reads + 1 write per lattice update (14 x element
@@ -252,6 +254,8 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
         "upload_s": upload_s, "pcie_inclusive_glups": updates / (wall + upload_s) / 1e9,
         "traffic": traffic, "config": cfg, "tuned_ms": tuned_ms, "accuracy": acc,
         "last_gosa": float(s.gosa_history[-1]), "steps": steps,
+        "step_ms_device": {"median": float(np.median(step_ms)), "min": float(min(step_ms)),
+                           "max": float(max(step_ms))},
     }
     s.close()
     return res, arrays
@@ -458,6 +462,7 @@ def main():
                      "bytes_per_launch": res["bytes_per_launch"],
                      "avg_launch_ms": res["avg_launch_ms"], "measured_ceilings": res["ceilings"]},
         "hbm_gbps_alg": res["hbm_gbps_alg"],
+        "step_ms_device": res["step_ms_device"],
         "accuracy": res["accuracy"],
         "upload_s": res["upload_s"],
         "pcie_inclusive_glups": res["pcie_inclusive_glups"],
