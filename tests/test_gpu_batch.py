@@ -145,6 +145,23 @@ def test_batch_graph_replays_match_eager(tsteps):
             assert np.array_equal(x, y)
 
 
+def test_batch_of_one_and_zero_iterations():
+    shape = (20, 21, 70)
+    f = inputs.fields(9, shape)
+    say("batch of one")
+    with hj.Batch("f64", [shape]) as b:
+        b.config = hj.Config.make(kernel=1, bj=14, vec=4, ichunk=6, nontemporal=0, use_graph=1, xcd_remap=1,
+                                  persistent=0, tsteps=2, reread=0)
+        b.upload_all(0, f)
+        b.sweep(0, 0.8)                          # no-op
+        assert np.array_equal(b.download(0), f["p"])
+        assert b.residual()[0] == pytest.approx(oracle.residual(f), rel=1e-10)
+        b.sweep(5, 0.8)
+        pref, _, href = oracle.sweep(f, 5, 0.8)
+        assert np.array_equal(b.download(0), pref)
+        assert gosa_err(b.gosa_history[:, 0], href) <= F64_GOSA_RTOL
+
+
 def test_batch_autotune_keeps_parity():
     shapes, seeds = small_batch(1, 5)
     arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
