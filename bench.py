@@ -399,6 +399,8 @@ def main():
     ap.add_argument("--no-ceilings", dest="ceilings", action="store_false",
                     help="skip the copy and 13-read/1-write bandwidth probes")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-dtype", default="f32", choices=["f32", "f64"],
+                    help="dtype of the batch64 workload when it runs alone (--profile --workload batch64)")
     ap.add_argument("--config", default="",
                     help="run the main workload in this configuration instead of the tuned one, "
                          "as field=value pairs, e.g. tsteps=1,vec=2,bj=4,ichunk=2,nontemporal=1")
@@ -424,8 +426,8 @@ def main():
         if not args.profile:
             raise SystemExit("the main line is a single solve; batch64 is reported under extra "
                              "(or run it alone with --profile)")
-        r = run_batch(args, hj, inputs, "f32", w.iters, False, args.retune)
-        print(json.dumps({"workload": w.name, "batch64_f32_batched": r}), flush=True)
+        r = run_batch(args, hj, inputs, args.batch_dtype, w.iters, False, args.retune)
+        print(json.dumps({"workload": w.name, "batch64_%s_batched" % args.batch_dtype: r}), flush=True)
         return
     if args.profile:
         args.no_cpu_baseline = True
