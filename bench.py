@@ -135,19 +135,19 @@ def accuracy(w, arrays, p_gpu, hist_gpu, iters: int):
             "field_bitwise": bool(np.array_equal(p_gpu.astype(np.float64), pref))}
 
 
-def sampled_accuracy(w, inputs, p2, m: int = 2000):
-    """Field error after two sweeps on sampled cells, each recomputed by the
-    oracle on its own 5x5x5 neighbourhood (grids too large to sweep on the host)."""
+def sampled_accuracy(w, inputs, pn, n: int, m: int = 2000):
+    """Field error after n sweeps on sampled cells, each recomputed by the
+    oracle on its own (2n+1)^3 neighbourhood (grids too large to sweep on the host)."""
     import oracle
     rng = np.random.default_rng(11)
-    cells = np.stack([rng.integers(2, n - 2, m) for n in w.shape], 1)
+    cells = np.stack([rng.integers(n, s - n, m) for s in w.shape], 1)
     nb = inputs.neighbourhood(w.seed, w.shape, cells,
-                              dtype=np.float64 if w.dtype == "f64" else np.float32, radius=2)
-    ref = np.array([oracle.sweep({n: nb[n][q] for n in inputs.INPUTS}, 2, w.omega)[0][2, 2, 2]
+                              dtype=np.float64 if w.dtype == "f64" else np.float32, radius=n)
+    ref = np.array([oracle.sweep({f: nb[f][q] for f in inputs.INPUTS}, n, w.omega)[0][n, n, n]
                     for q in range(m)])
-    got = p2[cells[:, 0], cells[:, 1], cells[:, 2]].astype(np.float64)
+    got = pn[cells[:, 0], cells[:, 1], cells[:, 2]].astype(np.float64)
     return {"field_rel_err": float(np.abs(got - ref).max() / np.abs(ref).max()),
-            "iters_checked": 2, "cells_checked": m}
+            "iters_checked": n, "cells_checked": m}
 
 
 def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, keep_arrays: bool):
@@ -197,12 +197,14 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
     # accuracy of the first solve from the initial field
     acc = None
     if check_iters:
-        n_chk = min(check_iters, w.iters) if arrays is not None else 2
+        # whole grids: the first check_iters iterations; sampled cells: one
+        # pass of the configured kernel
+        n_chk = min(check_iters, w.iters) if arrays is not None else max(2, int(cfg.get("tsteps", 1)))
         s.sweep(n_chk, w.omega)
         if arrays is not None:
             acc = accuracy(w, arrays, s.download("p"), s.gosa_history.copy(), n_chk)
         else:
-            acc = sampled_accuracy(w, inputs, s.download("p"))
+            acc = sampled_accuracy(w, inputs, s.download("p"), n_chk)
         log("accuracy", acc)
         if arrays is not None:
             s.upload("p", arrays["p"])
@@ -226,10 +228,10 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
     updates = n_int * w.iters * steps
     glups = updates / wall / 1e9
     # Algorithmic bytes: 13 reads + 1 write per lattice update (14 x element
-    # size). A two-iteration launch updates every interior cell twice; the
-    # odd remainder of a solve runs one single-iteration launch, whose time is
-    # folded in pro rata (one iteration = half a two-iteration launch).
-    tsteps = 2 if cfg.get("tsteps") == 2 else 1
+    # size). A launch of t iterations updates every interior cell t times; a
+    # remainder of a solve runs single-iteration launches, whose time is
+    # folded in pro rata (one iteration = 1/t of a launch).
+    tsteps = max(1, int(cfg.get("tsteps", 1)))
     launches = w.iters * steps / tsteps
     bytes_per_launch = 14 * esize(w.dtype) * n_int * tsteps
     avg_launch_ms = kernel_ms / launches
@@ -460,7 +462,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": res["hbm_gbps_alg"], "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": res["frac_peak"], "traffic": res["traffic"],
                      "kernel": kernel_name(res["config"]),
-                     "lattice_updates_per_launch": interior(w.shape) * (2 if res["config"].get("tsteps") == 2 else 1),
+                     "lattice_updates_per_launch": interior(w.shape) * max(1, int(res["config"].get("tsteps", 1))),
                      "bytes_per_launch": res["bytes_per_launch"],
                      "avg_launch_ms": res["avg_launch_ms"], "measured_ceilings": res["ceilings"]},
         "hbm_gbps_alg": res["hbm_gbps_alg"],

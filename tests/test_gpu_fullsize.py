@@ -1,8 +1,9 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (the tuning cache the benchmark reads, or the defaults when it has no
 entry). Grids the oracle can sweep are compared whole; the 514x514x1026
-grid is compared after two iterations on sampled cells, each recomputed by
-the oracle on its own 5x5x5 neighbourhood (drawn from the counter-based
+grid is compared after one pass of the configured kernel (two or three
+iterations) on sampled cells, each recomputed by the oracle on its own
+(2n+1)^3 neighbourhood for n iterations (drawn from the counter-based
 generator), plus properties that hold at any size."""
 import os
 
@@ -53,17 +54,17 @@ def test_large_f32_full_grid():
     assert gosa_err(hist, href) < 1e-4
 
 
-def sample_cells(shape, m, rng):
-    """Cells at least two from the shell (their 5x5x5 block is in the grid),
+def sample_cells(shape, m, rng, r=2):
+    """Cells at least r from the shell (their (2r+1)^3 block is in the grid),
     with the corners, edges and last k tile of that region."""
     nx, ny, nz = shape
-    pts = [np.stack([rng.integers(2, s - 2, m) for s in shape], 1)]
-    for i in (2, nx - 3):
-        for j in (2, ny - 3):
-            for k in (2, 3, nz - 4, nz - 3):
+    pts = [np.stack([rng.integers(r, s - r, m) for s in shape], 1)]
+    for i in (r, nx - 1 - r):
+        for j in (r, ny - 1 - r):
+            for k in (r, r + 1, nz - 2 - r, nz - 1 - r):
                 pts.append(np.array([[i, j, k]]))
-    pts.append(np.stack([rng.integers(2, nx - 2, 64), rng.integers(2, ny - 2, 64),
-                         np.full(64, nz - 3)], 1))
+    pts.append(np.stack([rng.integers(r, nx - r, 64), rng.integers(r, ny - r, 64),
+                         np.full(64, nz - 1 - r)], 1))
     return np.concatenate(pts)
 
 
@@ -74,20 +75,21 @@ def test_huge_f32_sampled_cells_and_properties():
     with hj.Solver("f32", shape) as s:
         for name in inputs.INPUTS:          # one field at a time: about 1 GiB each
             s.upload(name, inputs.field(w.seed, name, shape, dtype=np.float32))
-        say("huge_f32 sweep 2", s.config)
-        s.sweep(2, w.omega)                 # one launch of a two-iteration configuration
+        n1 = max(2, s.config.tsteps)        # one pass of the configured kernel
+        say("huge_f32 sweep", n1, s.config)
+        s.sweep(n1, w.omega)
         p1 = s.download("p")
         say("huge_f32 sweep 3 more")
         s.sweep(3, w.omega)
         hist = s.gosa_history.copy()
         g_after = s.residual()
     rng = np.random.default_rng(5)
-    cells = sample_cells(shape, 3000, rng)
-    nb = inputs.neighbourhood(w.seed, shape, cells, dtype=np.float32, radius=2)
+    cells = sample_cells(shape, 3000, rng, r=n1)
+    nb = inputs.neighbourhood(w.seed, shape, cells, dtype=np.float32, radius=n1)
     ref = np.empty(len(cells))
     for q in range(len(cells)):
         blk = {n: nb[n][q] for n in inputs.INPUTS}
-        ref[q] = oracle.sweep(blk, 2, w.omega)[0][2, 2, 2]
+        ref[q] = oracle.sweep(blk, n1, w.omega)[0][n1, n1, n1]
     got = p1[cells[:, 0], cells[:, 1], cells[:, 2]].astype(np.float64)
     assert np.abs(got - ref).max() <= F32_FIELD_RTOL * np.abs(ref).max()
     # the shell is never written

@@ -331,14 +331,15 @@ def test_neighbourhood_blocks_reproduce_full_sweep():
         assert oracle.sweep(blk, 1, 0.8)[0][1, 1, 1] == p1[i, j, k]
 
 
-def test_radius_two_blocks_reproduce_two_sweeps():
-    """After two Jacobi iterations a cell depends only on its 5x5x5 block."""
+@pytest.mark.parametrize("n", [2, 3])
+def test_radius_n_blocks_reproduce_n_sweeps(n):
+    """After n Jacobi iterations a cell depends only on its (2n+1)^3 block."""
     shape = (11, 12, 13)
     f = inputs.fields(7, shape)
-    p2, _, _ = oracle.sweep(f, 2, 0.8)
+    pn, _, _ = oracle.sweep(f, n, 0.8)
     rng = np.random.default_rng(2)
-    cells = np.stack([rng.integers(2, s - 2, 30) for s in shape], 1)
-    nb = inputs.neighbourhood(7, shape, cells, radius=2)
+    cells = np.stack([rng.integers(n, s - n, 30) for s in shape], 1)
+    nb = inputs.neighbourhood(7, shape, cells, radius=n)
     for q, (i, j, k) in enumerate(cells):
-        blk = {n: nb[n][q] for n in inputs.INPUTS}
-        assert oracle.sweep(blk, 2, 0.8)[0][2, 2, 2] == p2[i, j, k]
+        blk = {f_: nb[f_][q] for f_ in inputs.INPUTS}
+        assert oracle.sweep(blk, n, 0.8)[0][n, n, n] == pn[i, j, k]
