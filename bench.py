@@ -34,8 +34,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 TUNE_CACHE = os.path.join(ROOT, "paper_2002_12115_amd", "tune_cache.txt")
 
 
+_T0 = time.perf_counter()
+
+
 def log(*a):
-    print("[bench]", *a, file=sys.stderr, flush=True)
+    print("[bench +%.1fs]" % (time.perf_counter() - _T0), *a, file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
