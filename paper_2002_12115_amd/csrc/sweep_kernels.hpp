@@ -11,12 +11,18 @@
 // built around HBM streams, not arithmetic:
 //  * one wave covers 64*V consecutive k of one j row (k is contiguous), so
 //    every stream is a coalesced 512 B (FP64) or 1 KiB (FP32, V=4) access;
-//  * the 12 arrays read once per sweep (a0..c2, bnd, wrk1) and wrk2 use
-//    non-temporal loads/stores so they do not evict p from L2;
 //  * p, the only array with neighbour reuse, is staged per (j,k) tile in an
 //    LDS ring of 4 planes while the workgroup marches along i: each p value
-//    is fetched from memory once per tile (plus a one-cell halo), and the
-//    19 neighbours are read from LDS or from the lane's own registers;
+//    is fetched from memory once per tile (plus a halo), and the 19
+//    neighbours are read from LDS or from the lane's own registers;
+//  * one iteration per pass (march kernel): the 12 arrays read once per
+//    sweep (a0..c2, bnd, wrk1) and wrk2 use non-temporal loads/stores so
+//    they do not evict p from L2;
+//  * two iterations per pass (fused and wide kernels, the faster ones):
+//    the first iteration of a tile and its halo goes to a second LDS ring
+//    and the second is computed from it, so the coefficient arrays are read
+//    once per two iterations; neighbouring tiles run on the same XCD, so
+//    their shared halo reads hit its L2;
 //  * the gosa partial of each tile is reduced in registers (64-lane xor
 //    butterfly) and LDS, then written to its own slot, and a second kernel
 //    sums the slots in a fixed order: the result does not depend on timing.
