@@ -237,6 +237,32 @@ def test_autotune_restores_state_and_keeps_parity():
             assert field_err(p, pref) <= F32_FIELD_RTOL
 
 
+def test_tuning_cache_round_trip(tmp_path, monkeypatch):
+    """The autotune winner is recorded in HJ_TUNE_CACHE and a new handle for
+    the same problem starts from it; malformed lines, other shapes and
+    unsupported configurations in the file are ignored."""
+    path = tmp_path / "cache.txt"
+    shape = (40, 36, 140)
+    path.write_text("not a cache line\n"
+                    "solve gfx950 f64 9x9x9 1 4 2 2 1 0 0 0.1 1 0\n"
+                    "solve gfx950 f64 40x36x140 1 3 7 2 1 0 0 0.1 1 0\n")   # bj 3, vec 7: unsupported
+    monkeypatch.setenv("HJ_TUNE_CACHE", str(path))
+    f = inputs.fields(3, shape)
+    with hj.Solver("f64", shape) as s:
+        assert s.config.bj != 3                 # the unsupported line was not applied
+        s.upload_all(f)
+        say("cache round trip")
+        best, _ = s.autotune(n_sweeps=2, repeats=1)
+    lines = [ln for ln in path.read_text().splitlines() if " 40x36x140 " in ln]
+    assert len(lines) == 1                      # the winner replaced the old line for this shape
+    assert "not a cache line" in path.read_text() and " 9x9x9 " in path.read_text()
+    with hj.Solver("f64", shape) as s:
+        assert s.config.as_dict() == dict(best.as_dict(), use_graph=1)
+        s.upload_all(f)
+        s.sweep(3, 0.8)
+        assert np.array_equal(s.download("p"), oracle.sweep(f, 3, 0.8)[0])
+
+
 def test_genetic_search_restores_state_and_keeps_parity():
     shape = (40, 36, 140)
     f = inputs.fields(7, shape)
