@@ -149,7 +149,12 @@ int hj_residual(hj_solver h, double* gosa);
 
 /* The configuration the next sweep runs with: the library default, the
  * tuning cache's entry for this problem, the last autotune winner or the
- * last hj_set_config. hj_set_config returns HJ_ERR_ARG for a configuration
+ * last hj_set_config. The default of a new solve is the two-iteration
+ * kernel on 64-cell rows (kernel HJ_KERNEL_MARCH, bj 8, vec 2, tsteps 2,
+ * reread 0, nontemporal 0, xcd_remap 1, use_graph 1) with the i-chunk that
+ * keeps its grid to one wave of resident workgroups on the device; when the
+ * occupancy query fails, the one-iteration kernel (bj 4 (FP64) or 8 (FP32),
+ * vec 2 or 4, nontemporal 1, tsteps 1). hj_set_config returns HJ_ERR_ARG for a configuration
  * the library does not build (see hj_config) or a flat kernel that does not
  * fit the grid, and leaves the previous one in place. */
 int hj_get_config(hj_solver h, hj_config* out);

@@ -68,6 +68,9 @@ int guarded(F&& f)
     try {
         return f();
     } catch (const HipFail& h) {
+        // clear the runtime's last error, so a later, unrelated launch check
+        // does not report this one again (non-sticky errors such as OOM)
+        (void)hipGetLastError();
         const int code = (h.e == hipErrorOutOfMemory || h.e == hipErrorMemoryAllocation) ? HJ_ERR_OOM : HJ_ERR_HIP;
         return set_err(code, "%s failed at hj_api.hip:%d: %s (%s)", h.expr, h.line,
                        hipGetErrorName(h.e), hipGetErrorString(h.e));
@@ -128,8 +131,10 @@ int check_dtype(int dtype)
     return HJ_OK;
 }
 
-// Starting point before any tuning (the best measured family on MI355X:
-// non-temporal streams, 16-byte lanes, short i chunks; see the tune log).
+// The one-iteration configuration: the base of the tuner's candidates and
+// of gene decoding, and the kernel that runs the odd remainder iteration
+// and the residual of two-iteration solves (non-temporal streams, 16-byte
+// lanes, short i chunks: the best measured one-iteration family on MI355X).
 hj_config default_config(int dtype)
 {
     hj_config c;
@@ -1074,10 +1079,40 @@ int default_ichunk(int dtype, const hj_config& c, int nx, int ny, int nz)
     return (int)std::max<long long>(1, (nx - 2 + nchunks - 1) / nchunks);
 }
 
-// Default configuration, or the tuning cache's entry for this problem.
+// Starting configuration of a new single solve before any tuning: two
+// iterations per pass on 64-cell rows with a halo wave (8 rows per tile,
+// coefficients kept in registers, XCD-aware tile numbering), in the longest
+// i-chunk that keeps the grid to one wave of resident workgroups. Of this
+// family it is the measured best on the 128^2x256 and 256^2x512 interiors and
+// within 5% of the best on 512^2x1024. Falls back to the one-iteration kernel
+// when the grid or the device query rules it out.
+hj_config start_config(int dtype, int nx, int ny, int nz)
+{
+    hj_config c = default_config(dtype);
+    c.kernel = HJ_KERNEL_MARCH;
+    c.bj = 8;
+    c.vec = 2;
+    c.tsteps = 2;
+    c.reread = 0;
+    c.nontemporal = 0;
+    c.xcd_remap = 1;
+    int dev = 0, cus = 0;
+    const int occ = dtype == HJ_F64 ? fused_occupancy<double>(c) : fused_occupancy<float>(c);
+    if (occ > 0 && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+        c.ichunk = ichunk_within(c, nx, ny, nz, (long long)occ * cus);
+        if (config_fits(dtype, c, nx, ny, nz)) return c;
+    }
+    (void)hipGetLastError();
+    c = default_config(dtype);
+    c.ichunk = default_ichunk(dtype, c, nx, ny, nz);
+    return c;
+}
+
+// Starting configuration, or the tuning cache's entry for this problem.
 void apply_start_config(hj_solver h)
 {
-    h->cfg.ichunk = default_ichunk(h->dtype, h->cfg, h->L.nx, h->L.ny, h->L.nz);
+    h->cfg = start_config(h->dtype, h->L.nx, h->L.ny, h->L.nz);
     hj_config c;
     if (cache_get("solve", h->dtype, solve_key(h->L.nx, h->L.ny, h->L.nz), c) &&
         config_fits(h->dtype, c, h->L.nx, h->L.ny, h->L.nz)) {

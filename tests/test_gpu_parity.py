@@ -118,11 +118,12 @@ def test_residual_matches_oracle_and_history():
 
 
 GRAPH_CONFIGS = [None,
+                 dict(kernel=1, bj=4, vec=2, ichunk=4, nontemporal=1, xcd_remap=0, tsteps=1, reread=0),
                  dict(kernel=1, bj=8, vec=2, ichunk=7, nontemporal=0, xcd_remap=1, tsteps=2, reread=0),
                  dict(kernel=1, bj=14, vec=4, ichunk=9, nontemporal=0, xcd_remap=1, tsteps=2, reread=1)]
 
 
-@pytest.mark.parametrize("extra", GRAPH_CONFIGS, ids=["default", "wide", "narrow"])
+@pytest.mark.parametrize("extra", GRAPH_CONFIGS, ids=["default", "one", "wide", "narrow"])
 def test_graph_replays_match_eager(extra):
     """Replays of captured loops (two cached graphs alternate when a call has
     an odd number of passes) equal eager launches, with host work between."""
@@ -164,6 +165,28 @@ def test_sweep_in_pieces_equals_one_call():
         assert np.array_equal(s.download("wrk2"), p_pieces)
     pref, href = oracle_run(shape, 11, seed=1)
     assert np.array_equal(p_pieces, pref)
+    assert gosa_err(h, href) <= F64_GOSA_RTOL
+
+
+def test_default_is_the_two_iteration_kernel():
+    """A new solve with no tuning-cache entry starts on the two-iteration
+    kernel (64-cell rows, 8 rows per tile) and, with odd and even counts,
+    gives the oracle's field."""
+    shape = (66, 40, 130)
+    f = inputs.fields(5, shape)
+    with hj.Solver("f64", shape) as s:
+        c = s.config
+        assert (c.kernel, c.bj, c.vec, c.tsteps, c.reread, c.xcd_remap) == (1, 8, 2, 2, 0, 1)
+        assert 1 <= c.ichunk <= shape[0] - 2
+        s.upload_all(f)
+        say("default config", c)
+        s.sweep(5, 0.8)
+        h = list(s.gosa_history)
+        s.sweep(4, 0.8)
+        h.extend(s.gosa_history)
+        p = s.download("p")
+    pref, href = oracle_run(shape, 9, seed=5)
+    assert np.array_equal(p, pref)
     assert gosa_err(h, href) <= F64_GOSA_RTOL
 
 
@@ -214,6 +237,23 @@ def test_error_paths():
         h = s._h
     lib = hj.load()
     assert lib.hj_sweep(h, 1, 0.8, None, None) == -7     # destroyed handle
+
+
+def test_out_of_memory_is_reported_and_recoverable():
+    """A grid larger than the device (about 3 TB of arrays) fails with
+    HJ_ERR_OOM, and later handles work normally (the error is not kept)."""
+    with pytest.raises(hj.HJError) as e:
+        hj.Solver("f64", (3000, 3000, 3000), use_torch=False)
+    assert e.value.status == -4
+    with pytest.raises(hj.HJError) as e:
+        hj.Batch("f64", [(20, 20, 20), (3000, 3000, 3000)])
+    assert e.value.status == -4
+    shape = (12, 13, 70)
+    f = inputs.fields(4, shape)
+    with hj.Solver("f64", shape, use_torch=False) as s:
+        s.upload_all(f)
+        s.sweep(3, 0.8)
+        assert np.array_equal(s.download("p"), oracle.sweep(f, 3, 0.8)[0])
 
 
 def test_autotune_restores_state_and_keeps_parity():
@@ -287,6 +327,10 @@ def test_genetic_search_restores_state_and_keeps_parity():
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_transfer_placements_give_the_same_solve(dtype):
+    """Every host-transfer placement gives the resident solve's field bit for
+    bit. gosa agrees to rounding: a placement that sweeps one iteration per
+    call runs those on the one-iteration kernel, whose per-tile partials are
+    summed in another order than the two-iteration kernel's."""
     from paper_2002_12115_amd import transfer
     shape = (34, 34, 66)
     f = inputs.fields(2002, shape)
@@ -298,7 +342,7 @@ def test_transfer_placements_give_the_same_solve(dtype):
     ref = res["resident"]
     for policy, r in res.items():
         assert np.array_equal(r["field"], ref["field"]), policy
-        assert np.array_equal(r["gosa_history"], ref["gosa_history"]), policy
+        assert gosa_err(r["gosa_history"], ref["gosa_history"]) <= 1e-13, policy
     assert res["p_every_iter"]["d2h_bytes"] == 12 * f["p"].size * (8 if dtype == "f64" else 4)
     if dtype == "f64":
         pref, _ = oracle_run(shape, 12)
