@@ -310,6 +310,19 @@ def transfer_ablation(w, hj, arrays):
     return out
 
 
+def one_iteration_config(hj, dtype: str, shape) -> dict:
+    """The plain one-iteration configuration of a single solve (one launch per
+    iteration): march kernel, 16-byte lanes (bj 4 for FP64, 8 for FP32),
+    non-temporal streams, the i-chunk that gives the grid about 4096 workgroups."""
+    bj, vec = (4, 2) if dtype == "f64" else (8, 4)
+    kt = -(-(shape[2] - 2) // (64 * vec))
+    jt = -(-(shape[1] - 2) // bj)
+    nchunks = max(1, -(-4096 // (kt * jt)))
+    ichunk = max(1, -(-(shape[0] - 2) // nchunks))
+    return dict(kernel=hj.KERNEL_MARCH, bj=bj, vec=vec, ichunk=ichunk, nontemporal=1, use_graph=0, xcd_remap=0,
+                persistent=0, tsteps=1, reread=0)
+
+
 def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune: bool):
     w = inputs.WORKLOADS["batch64"]
     shapes, seeds = inputs.batch_shapes(w.seed, w.batch)
@@ -322,7 +335,7 @@ def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune
         for sh, sd in zip(shapes, seeds):
             s = hj.Solver(dtype, sh, stream=stream)   # all instances on one stream
             stream = stream or s.stream
-            s.set(use_graph=0)
+            s.config = hj.Config.make(**one_iteration_config(hj, dtype, sh))
             s.upload_all(inputs.fields(sd, sh))
             solvers.append(s)
         for s in solvers:
@@ -337,9 +350,9 @@ def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune
             for s in solvers:
                 s.sync()
         wall = time.perf_counter() - t0
+        cfg = dict(one_iteration_config(hj, dtype, shapes[0]), ichunk="about 4096 workgroups per instance")
         for s in reversed(solvers):          # the first one owns the shared stream
             s.close()
-        cfg = None
     else:
         b = hj.Batch(dtype, shapes)
         for t, (sh, sd) in enumerate(zip(shapes, seeds)):

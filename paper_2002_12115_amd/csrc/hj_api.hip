@@ -115,7 +115,7 @@ bool make_layout(int dtype, int nx, int ny, int nz, Layout& L)
     L.nx = nx; L.ny = ny; L.nz = nz;
     L.esz = dtype == HJ_F64 ? 8 : 4;
     L.A = 128 / L.esz;
-    L.P = ((long long)L.A + nz + 4 + L.A - 1) / L.A * L.A;
+    L.P = pitch_of(L.esz, nz);
     L.S = (long long)ny * L.P;
     const long double bytes = (long double)nx * L.S * L.esz;
     if (bytes > (long double)(1ULL << 46)) return false;

@@ -133,7 +133,9 @@ bool config_fits(int dtype, const hj_config& c, int nx, int ny, int nz)
 {
     (void)nx;
     if (!config_supported(dtype, c)) return false;
-    if (c.kernel == HJ_KERNEL_FLAT) return flat_fits(dtype == HJ_F64 ? 8 : 4, c.bj, ny, nz);
+    const int esz = dtype == HJ_F64 ? 8 : 4;
+    if (c.kernel == HJ_KERNEL_FLAT) return flat_fits(esz, c.bj, ny, nz);
+    if (fused_of(c) && c.vec == 2) return wide_plane_ok(esz, ny, nz);
     return true;
 }
 
@@ -276,6 +278,7 @@ hipError_t fused_batch_go(const hj_config& c, const Instance<T>* inst, const int
 template <typename T, int BJ, bool NT, bool KEEP>
 hipError_t wide_go(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2, hipStream_t st)
 {
+    if (!wide_plane_ok((int)sizeof(T), g.ny, g.nz)) return hipErrorInvalidValue;  // 32-bit offsets (FP32)
     const TileCounts t = tile_counts(c, g.nx, g.ny, g.nz);
     const long long nb = t.tiles();
     if (nb <= 0) return hipSuccess;

@@ -32,6 +32,23 @@ constexpr bool fused_bj_ok(int vec, int bj)
                       : false;
 }
 
+// Pitch of a k row in elements: a front pad of A-1 elements (A = 128 B of
+// elements) puts interior k=1 on a 128-byte boundary; the row, with 4 spare
+// elements, is rounded up to a multiple of A.
+inline long long pitch_of(int esz, int nz)
+{
+    const long long A = 128 / esz;
+    return (A + nz + 4 + A - 1) / A * A;
+}
+
+// The FP32 kernel of the 64-cell-row two-iteration layout addresses a plane
+// with 32-bit byte offsets: a plane (ny rows of the pitch) must hold fewer
+// than 2^32 bytes. The FP64 kernel uses 64-bit offsets.
+inline bool wide_plane_ok(int esz, int ny, int nz)
+{
+    return esz == 8 || (long long)ny * pitch_of(esz, nz) * esz < (1LL << 32);
+}
+
 // LDS bytes per staged plane of the flat kernel.
 constexpr int kFlatPlaneBytesHost = 10240;
 
