@@ -135,7 +135,7 @@ bool config_fits(int dtype, const hj_config& c, int nx, int ny, int nz)
     if (!config_supported(dtype, c)) return false;
     const int esz = dtype == HJ_F64 ? 8 : 4;
     if (c.kernel == HJ_KERNEL_FLAT) return flat_fits(esz, c.bj, ny, nz);
-    if (fused_of(c) && c.vec == 2) return wide_plane_ok(esz, ny, nz);
+    if (fused_of(c)) return plane32_ok(esz, ny, nz);
     return true;
 }
 
@@ -255,6 +255,7 @@ template <typename T, int BJ, int W, bool NT, bool KEEP>
 hipError_t fused_go(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                     hipStream_t st)
 {
+    if (!plane32_ok((int)sizeof(T), g.ny, g.nz)) return hipErrorInvalidValue;  // 32-bit offsets (FP32)
     const TileCounts t = tile_counts(c, g.nx, g.ny, g.nz);
     const long long nb = t.tiles();
     if (nb <= 0) return hipSuccess;
@@ -278,7 +279,7 @@ hipError_t fused_batch_go(const hj_config& c, const Instance<T>* inst, const int
 template <typename T, int BJ, bool NT, bool KEEP>
 hipError_t wide_go(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2, hipStream_t st)
 {
-    if (!wide_plane_ok((int)sizeof(T), g.ny, g.nz)) return hipErrorInvalidValue;  // 32-bit offsets (FP32)
+    if (!plane32_ok((int)sizeof(T), g.ny, g.nz)) return hipErrorInvalidValue;  // 32-bit offsets (FP32)
     const TileCounts t = tile_counts(c, g.nx, g.ny, g.nz);
     const long long nb = t.tiles();
     if (nb <= 0) return hipSuccess;

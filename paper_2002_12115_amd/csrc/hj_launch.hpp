@@ -41,10 +41,10 @@ inline long long pitch_of(int esz, int nz)
     return (A + nz + 4 + A - 1) / A * A;
 }
 
-// The FP32 kernel of the 64-cell-row two-iteration layout addresses a plane
-// with 32-bit byte offsets: a plane (ny rows of the pitch) must hold fewer
-// than 2^32 bytes. The FP64 kernel uses 64-bit offsets.
-inline bool wide_plane_ok(int esz, int ny, int nz)
+// The FP32 two-iteration kernels address a plane with 32-bit byte offsets: a
+// plane (ny rows of the pitch) must hold fewer than 2^32 bytes. The FP64
+// kernels use 64-bit offsets.
+inline bool plane32_ok(int esz, int ny, int nz)
 {
     return esz == 8 || (long long)ny * pitch_of(esz, nz) * esz < (1LL << 32);
 }

@@ -392,6 +392,194 @@ __global__ __launch_bounds__(kWave * BJ) void direct_kernel(Grid<T> g, T omega, 
     if (threadIdx.x == 0) part[L] = acc;
 }
 
+// Load at a 32-bit byte offset from a workgroup-uniform base (the base stays
+// in scalar registers; the offset is one VGPR).
+template <typename T, bool NT>
+__device__ __forceinline__ T oload(const T* base, unsigned off)
+{
+    return sload<T, NT>(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off));
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Which two-iteration tiles prefetch (tile2_prefetch): the FP32 single-solve
+// kernels. FP64 cannot hold the extra register set, and the batch kernels'
+// short chunks of small grids lose more to the deeper prologue and the
+// loads past each chunk's end than they gain (measured: batch64 FP32 -9%).
+template <typename T>
+constexpr bool kPrefetchSingle = sizeof(T) == 4;
+
+// A thread's first-iteration cell in a two-iteration tile whose p0 tile
+// starts at (j0-2, k0-2): grid cell (j, k), its place (rho, c) in the p0 tile
+// and (r1, c1) in the p1 tile; active: the thread has a cell; own: its cell
+// is one the tile updates in the second iteration (when interior).
+struct TileCell {
+    int j, k, rho, c, r1, c1;
+    bool active, own;
+};
+
+// The FP32 form of the two-iteration tile, for every row layout: every
+// global load is unconditional, from an address clamped into the grid (a
+// value that lands outside the grid is never used), so the compiler counts
+// outstanding loads exactly and waits only for the ones a step consumes. The
+// p0 plane i+2+PD and the coefficients of plane i+PD are loaded while plane i
+// is computed, into PD+1 register sets that rotate from step to step, so a
+// load has PD whole steps to arrive. The p0 tile is fetched as a flat array
+// (two cells per thread). Byte offsets within a plane are 32-bit: a plane
+// must hold fewer than 2^32 bytes (plane32_ok).
+template <typename T, typename Lds, bool NT, bool KEEP, int PD>
+__device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0, int k0, const TileCell& tc, int ib,
+                                               int ie, Lds& sm, double& acc1, double& acc2)
+{
+    constexpr int NTH = kWave * Lds::NW;               // threads
+    constexpr int CELLS = Lds::R0 * Lds::W0;           // p0 tile cells, 2 per thread at most
+    static_assert(CELLS <= 2 * NTH && NTH <= CELLS, "p0 tile is fetched as two cells per thread");
+    const int tid = threadIdx.x;
+    const int j = tc.j, k = tc.k, rho = tc.rho, c = tc.c, r1 = tc.r1, c1 = tc.c1;
+    const bool active = tc.active;
+    const bool in_dom = active && (j <= g.ny - 1) && (k <= g.nz - 1);
+    const bool jk_int = in_dom && j >= 1 && j <= g.ny - 2 && k >= 1 && k <= g.nz - 2;
+    const bool out = tc.own && jk_int;                    // an output cell of this tile
+    const long long rowoff = (long long)j * g.P + k;
+
+    // byte offsets: the thread's cell (coefficients; an idle lane reads the
+    // cache line of the tile's first cell), its two p0 tile cells
+    const int jc = active ? j : j0 - 1, kc = active ? k : k0 - 1;
+    const unsigned coff =
+        (unsigned)(((long long)clampi(jc, 0, g.ny - 1) * g.P + clampi(kc, 0, g.nz - 1)) * (long long)sizeof(T));
+    unsigned poff[2];
+    int pcell[2];                                          // place in the p0 tile, -1: none
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int t = (tid + s * NTH < CELLS) ? tid + s * NTH : CELLS - 1;
+        const int r = t / Lds::W0, cc = t % Lds::W0;      // row j0-2+r, column k0-2+cc
+        poff[s] = (unsigned)(((long long)clampi(j0 - 2 + r, 0, g.ny - 1) * g.P + clampi(k0 - 2 + cc, 0, g.nz - 1)) *
+                             (long long)sizeof(T));
+        pcell[s] = tid + s * NTH < CELLS ? tid + s * NTH : -1;
+    }
+    auto plane = [&](int ii) { return (long long)clampi(ii, 0, g.nx - 1) * g.S; };
+    auto fetch = [&](int ii, T (&x)[2]) {
+        const T* b = g.src + plane(ii);
+        x[0] = oload<T, NT>(b, poff[0]);
+        x[1] = oload<T, NT>(b, poff[1]);
+    };
+    auto put = [&](int ii, const T (&x)[2]) {
+        T* f = &sm.p0[ii & 3][0][0];
+        if (pcell[0] >= 0) f[pcell[0]] = x[0];
+        if (pcell[1] >= 0) f[pcell[1]] = x[1];
+    };
+    auto coefs = [&](int ii, T (&x)[NCOEF]) {
+        const long long o = plane(ii);
+#pragma unroll
+        for (int q = 0; q < NCOEF; ++q) x[q] = oload<T, NT>(g.coef[q] + o, coff);
+    };
+
+    const int i_lo = ib - 1, i_hi = ie;                    // first-iteration planes
+    static_assert(PD == 1 || PD == 2, "prefetch distance");
+    constexpr int NS = PD + 1;                             // register sets
+    T ps[NS][2], cs[NS][NCOEF];
+    for (int ii = i_lo - 1; ii <= i_lo + 1; ++ii) {
+        fetch(ii, ps[0]);
+        put(ii, ps[0]);
+    }
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+        fetch(min(i_lo + 2 + d, i_hi + 1), ps[d]);
+        coefs(min(i_lo + d, i_hi), cs[d]);
+    }
+    // own cell's coefficients of plane i-1 for the second iteration: kept from
+    // the previous step (KEEP) or loaded again at the start of the step
+    T keep[NCOEF];
+#pragma unroll
+    for (int q = 0; q < NCOEF; ++q) keep[q] = T(0);
+    __syncthreads();
+
+    // one step: first iteration at plane i (coefficients cur, p0 planes
+    // i-1 .. i+1 in LDS), second iteration at plane i-1 on the own cells;
+    // loads p0 plane i+2+PD into pf and the coefficients of plane i+PD into
+    // nxt, and stores p0 plane i+2 (pp, loaded PD steps earlier) to LDS.
+    auto step = [&](int i, T (&cur)[NCOEF], T (&nxt)[NCOEF], T (&pf)[2], const T (&pp)[2]) {
+        if constexpr (!KEEP) coefs(i - 1, keep);
+        // planes past the chunk's last ones are not needed: load the last
+        // ones again (lines the workgroup has just read) instead
+        fetch(min(i + 2 + PD, i_hi + 1), pf);
+        coefs(min(i + PD, i_hi), nxt);
+
+        // ---- first iteration at plane i
+        const bool interior = jk_int && i >= 1 && i <= g.nx - 2;
+        if (in_dom) {
+            auto* Pm = sm.p0[(i - 1) & 3];
+            auto* Pc = sm.p0[i & 3];
+            auto* Pp = sm.p0[(i + 1) & 3];
+            T p1v;
+            if (interior) {
+                const T pc = Pc[rho][c];
+                const T ss = cell_ss<T>(cur[CA0], cur[CA1], cur[CA2], cur[CA3], cur[CB0], cur[CB1], cur[CB2],
+                                        cur[CC0], cur[CC1], cur[CC2], cur[CBND], cur[CWRK1],
+                                        Pp[rho][c], Pc[rho + 1][c], Pc[rho][c + 1],
+                                        bracket(Pp[rho + 1][c], Pp[rho - 1][c], Pm[rho + 1][c], Pm[rho - 1][c]),
+                                        bracket(Pc[rho + 1][c + 1], Pc[rho - 1][c + 1], Pc[rho + 1][c - 1],
+                                                Pc[rho - 1][c - 1]),
+                                        bracket(Pp[rho][c + 1], Pm[rho][c + 1], Pp[rho][c - 1], Pm[rho][c - 1]),
+                                        Pm[rho][c], Pc[rho - 1][c], Pc[rho][c - 1], pc);
+                p1v = pc + omega * ss;
+                if (out && i >= ib && i < ie) {
+                    const double d = (double)ss;
+                    acc1 += d * d;
+                }
+            } else {
+                p1v = Pc[rho][c];                              // the shell is never updated
+            }
+            sm.p1[i & 3][r1][c1] = p1v;
+        }
+        put(i + 2, pp);
+        __syncthreads();
+
+        // ---- second iteration at plane i-1, own cells
+        const int i2 = i - 1;
+        if (out && i2 >= ib && i2 < ie) {
+            auto* Qm = sm.p1[(i2 - 1) & 3];
+            auto* Qc = sm.p1[i2 & 3];
+            auto* Qp = sm.p1[(i2 + 1) & 3];
+            const T qc = Qc[r1][c1];
+            const T ss = cell_ss<T>(keep[CA0], keep[CA1], keep[CA2], keep[CA3], keep[CB0], keep[CB1], keep[CB2],
+                                    keep[CC0], keep[CC1], keep[CC2], keep[CBND], keep[CWRK1],
+                                    Qp[r1][c1], Qc[r1 + 1][c1], Qc[r1][c1 + 1],
+                                    bracket(Qp[r1 + 1][c1], Qp[r1 - 1][c1], Qm[r1 + 1][c1], Qm[r1 - 1][c1]),
+                                    bracket(Qc[r1 + 1][c1 + 1], Qc[r1 - 1][c1 + 1], Qc[r1 + 1][c1 - 1],
+                                            Qc[r1 - 1][c1 - 1]),
+                                    bracket(Qp[r1][c1 + 1], Qm[r1][c1 + 1], Qp[r1][c1 - 1], Qm[r1][c1 - 1]),
+                                    Qm[r1][c1], Qc[r1 - 1][c1], Qc[r1][c1 - 1], qc);
+            const T outv = qc + omega * ss;
+            T* dst = g.dst + (long long)i2 * g.S + rowoff;
+            if constexpr (NT) __builtin_nontemporal_store(outv, dst);
+            else *dst = outv;
+            const double d = (double)ss;
+            acc2 += d * d;
+        }
+        if constexpr (KEEP) {
+#pragma unroll
+            for (int q = 0; q < NCOEF; ++q) keep[q] = cur[q];
+        }
+    };
+
+    // step number K of each round of NS uses the register sets K, K+PD mod NS
+    auto stepk = [&](auto kc, int i) {
+        constexpr int K = decltype(kc)::value;
+        step(i, cs[K % NS], cs[(K + PD) % NS], ps[(K + PD) % NS], ps[K % NS]);
+    };
+    for (int i = i_lo;;) {
+        stepk(std::integral_constant<int, 0>{}, i);
+        if (++i > i_hi) break;
+        stepk(std::integral_constant<int, 1>{}, i);
+        if (++i > i_hi) break;
+        if constexpr (NS > 2) {
+            stepk(std::integral_constant<int, 2>{}, i);
+            if (++i > i_hi) break;
+        }
+    }
+}
+
 // ---- fused kernel: two Jacobi iterations per pass over HBM -------------------
 //
 // A workgroup owns a tile of BJ rows x (W-2) cells and marches along i. Its
@@ -423,6 +611,18 @@ struct alignas(16) FusedLds {
     T p1[4][R1][XW];
     double red[NW];
 };
+
+// The 62- and 30-cell-row layouts' cells: thread t on extended cell
+// (j0-1 + t/W, k0-1 + t%W); the own cells are rows 1..BJ, columns 1..W-2.
+template <int BJ, int W>
+__device__ __forceinline__ TileCell fused_cell(int j0, int k0)
+{
+    const int col = threadIdx.x % W, row = threadIdx.x / W;
+    TileCell t;
+    t.j = j0 - 1 + row; t.k = k0 - 1 + col; t.rho = row + 1; t.c = col + 1; t.r1 = row; t.c1 = col;
+    t.active = true; t.own = row >= 1 && row <= BJ && col >= 1 && col <= W - 2;
+    return t;
+}
 
 template <typename T>
 struct P0Regs {
@@ -590,7 +790,7 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
 
 // One workgroup's whole share of a two-iteration pass: tile (kt, jt), i-chunk
 // ic, both iterations' gosa partials to slot L of part1 / part2.
-template <typename T, int BJ, int W, bool NT, bool KEEP>
+template <typename T, int BJ, int W, bool NT, bool KEEP, bool PF>
 __device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, int jt, int ic, int ichunk, int L,
                                             FusedLds<T, BJ, W>& sm, double* __restrict__ part1,
                                             double* __restrict__ part2)
@@ -599,7 +799,13 @@ __device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, i
     int ie = ib + ichunk;
     if (ie > g.nx - 1) ie = g.nx - 1;
     double acc1 = 0.0, acc2 = 0.0;
-    fused_tile<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
+    if constexpr (!PF) {
+        fused_tile<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
+    } else {
+        const int k0 = 1 + kt * FusedLds<T, BJ, W>::TK, j0 = 1 + jt * BJ;
+        tile2_prefetch<T, FusedLds<T, BJ, W>, NT, KEEP, 2>(g, omega, j0, k0, fused_cell<BJ, W>(j0, k0), ib, ie, sm,
+                                                           acc1, acc2);
+    }
     constexpr int NW = FusedLds<T, BJ, W>::NW;
     acc1 = block_sum<NW>(acc1, sm.red);
     if (threadIdx.x == 0) part1[L] = acc1;
@@ -626,7 +832,7 @@ __global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fu
     const int kt = L % kt_n;
     const int jt = (L / kt_n) % jt_n;
     const int ic = L / (kt_n * jt_n);
-    fused_block<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
+    fused_block<T, BJ, W, NT, KEEP, kPrefetchSingle<T>>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
 }
 
 // Two iterations over every instance of a batch: one workgroup per tile of
@@ -650,7 +856,7 @@ __global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fu
     const int kt = t % d.kt_n;
     const int jt = (t / d.kt_n) % d.jt_n;
     const int ic = t / (d.kt_n * d.jt_n);
-    fused_block<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
+    fused_block<T, BJ, W, NT, KEEP, false>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
 }
 
 // ---- wide fused kernel: 64 own cells per row and a halo wave -----------------
@@ -862,191 +1068,27 @@ __device__ __forceinline__ void wide_tile_sync(const Grid<T>& g, T omega, int kt
     }
 }
 
-// Load at a 32-bit byte offset from a workgroup-uniform base (the base stays
-// in scalar registers; the offset is one VGPR).
-template <typename T, bool NT>
-__device__ __forceinline__ T oload(const T* base, unsigned off)
+// The 64-cell-row layout's cells: waves 0 .. BJ+1 on rows j0-1 .. j0+BJ,
+// lane l on column k0+l; wave BJ+2 on the halo columns k0-1 and k0+64 of
+// those rows (lane 2r+s: row j0-1+r, side s).
+template <int BJ>
+__device__ __forceinline__ TileCell wide_cell(int j0, int k0)
 {
-    return sload<T, NT>(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off));
-}
-
-__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-// The FP32 form: every global load of the tile is unconditional, from an
-// address clamped into the grid (a value that lands outside the grid is never
-// used), so the compiler counts outstanding loads exactly and waits only for
-// the ones a step consumes. The p0 plane i+2+PD and the coefficients of plane
-// i+PD are loaded while plane i is computed, into PD+1 register sets that
-// rotate from step to step, so a load has PD whole steps to arrive. Byte
-// offsets within a plane are 32-bit: a plane must hold fewer than 2^32 bytes
-// (wide_plane_ok).
-template <typename T, int BJ, bool NT, bool KEEP, int PD>
-__device__ __forceinline__ void wide_tile_prefetch(const Grid<T>& g, T omega, int kt, int jt, int ib, int ie,
-                                          WideLds<T, BJ>& sm, double& acc1, double& acc2)
-{
-    using Lds = WideLds<T, BJ>;
-    constexpr int NTH = kWave * Lds::NW;               // threads
-    constexpr int CELLS = Lds::R0 * Lds::W0;           // p0 tile cells, 2 per thread at most
-    static_assert(CELLS <= 2 * NTH && NTH <= CELLS, "p0 tile is fetched as two cells per thread");
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1), w = tid / kWave;
-    const int k0 = 1 + kt * kWave, j0 = 1 + jt * BJ;
-    const bool halo = (w == BJ + 2);
-    // this thread's first-iteration cell, its place in the p0 and p1 tiles
-    int j, k, rho, c, r1, c1;
-    bool active;
-    if (!halo) {
-        j = j0 - 1 + w; k = k0 + lane; rho = w + 1; c = lane + 2; r1 = w; c1 = lane + 1; active = true;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    TileCell t;
+    if (w != BJ + 2) {
+        t.j = j0 - 1 + w; t.k = k0 + lane; t.rho = w + 1; t.c = lane + 2; t.r1 = w; t.c1 = lane + 1;
+        t.active = true; t.own = w >= 1 && w <= BJ;
     } else {
         const int rr = lane >> 1, side = lane & 1;
-        j = j0 - 1 + rr; k = side ? k0 + kWave : k0 - 1; rho = rr + 1; c = side ? kWave + 2 : 1;
-        r1 = rr; c1 = side ? kWave + 1 : 0; active = lane < 2 * (BJ + 2);
+        t.j = j0 - 1 + rr; t.k = side ? k0 + kWave : k0 - 1; t.rho = rr + 1; t.c = side ? kWave + 2 : 1;
+        t.r1 = rr; t.c1 = side ? kWave + 1 : 0; t.active = lane < 2 * (BJ + 2); t.own = false;
     }
-    const bool in_dom = active && (j <= g.ny - 1) && (k <= g.nz - 1);
-    const bool jk_int = in_dom && j >= 1 && j <= g.ny - 2 && k >= 1 && k <= g.nz - 2;
-    const bool own = !halo && w >= 1 && w <= BJ;
-    const bool out = own && jk_int;                       // an output cell of this tile
-    const long long rowoff = (long long)j * g.P + k;
-
-    // byte offsets: the thread's cell (coefficients; an idle halo lane reads
-    // the cache line of lane 0's cell), its two p0 tile cells
-    const int jc = active ? j : j0 - 1, kc = active ? k : k0 - 1;
-    const unsigned coff =
-        (unsigned)(((long long)clampi(jc, 0, g.ny - 1) * g.P + clampi(kc, 0, g.nz - 1)) * (long long)sizeof(T));
-    unsigned poff[2];
-    int pcell[2];                                          // place in the p0 tile, -1: none
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const int t = (tid + s * NTH < CELLS) ? tid + s * NTH : CELLS - 1;
-        const int r = t / Lds::W0, cc = t % Lds::W0;      // row j0-2+r, column k0-2+cc
-        poff[s] = (unsigned)(((long long)clampi(j0 - 2 + r, 0, g.ny - 1) * g.P + clampi(k0 - 2 + cc, 0, g.nz - 1)) *
-                             (long long)sizeof(T));
-        pcell[s] = tid + s * NTH < CELLS ? tid + s * NTH : -1;
-    }
-    auto plane = [&](int ii) { return (long long)clampi(ii, 0, g.nx - 1) * g.S; };
-    auto fetch = [&](int ii, T (&x)[2]) {
-        const T* b = g.src + plane(ii);
-        x[0] = oload<T, NT>(b, poff[0]);
-        x[1] = oload<T, NT>(b, poff[1]);
-    };
-    auto put = [&](int ii, const T (&x)[2]) {
-        T* f = &sm.p0[ii & 3][0][0];
-        if (pcell[0] >= 0) f[pcell[0]] = x[0];
-        if (pcell[1] >= 0) f[pcell[1]] = x[1];
-    };
-    auto coefs = [&](int ii, T (&x)[NCOEF]) {
-        const long long o = plane(ii);
-#pragma unroll
-        for (int q = 0; q < NCOEF; ++q) x[q] = oload<T, NT>(g.coef[q] + o, coff);
-    };
-
-    const int i_lo = ib - 1, i_hi = ie;                    // first-iteration planes
-    static_assert(PD == 1 || PD == 2, "prefetch distance");
-    constexpr int NS = PD + 1;                             // register sets
-    T ps[NS][2], cs[NS][NCOEF];
-    for (int ii = i_lo - 1; ii <= i_lo + 1; ++ii) {
-        fetch(ii, ps[0]);
-        put(ii, ps[0]);
-    }
-#pragma unroll
-    for (int d = 0; d < PD; ++d) {
-        fetch(min(i_lo + 2 + d, i_hi + 1), ps[d]);
-        coefs(min(i_lo + d, i_hi), cs[d]);
-    }
-    // own cell's coefficients of plane i-1 for the second iteration: kept from
-    // the previous step (KEEP) or loaded again at the start of the step
-    T keep[NCOEF];
-#pragma unroll
-    for (int q = 0; q < NCOEF; ++q) keep[q] = T(0);
-    __syncthreads();
-
-    // one step: first iteration at plane i (coefficients cur, p0 planes
-    // i-1 .. i+1 in LDS), second iteration at plane i-1 on the own cells;
-    // loads p0 plane i+2+PD into pf and the coefficients of plane i+PD into
-    // nxt, and stores p0 plane i+2 (pp, loaded PD steps earlier) to LDS.
-    auto step = [&](int i, T (&cur)[NCOEF], T (&nxt)[NCOEF], T (&pf)[2], const T (&pp)[2]) {
-        if constexpr (!KEEP) coefs(i - 1, keep);
-        // planes past the chunk's last ones are not needed: load the last
-        // ones again (lines the workgroup has just read) instead
-        fetch(min(i + 2 + PD, i_hi + 1), pf);
-        coefs(min(i + PD, i_hi), nxt);
-
-        // ---- first iteration at plane i
-        const bool interior = jk_int && i >= 1 && i <= g.nx - 2;
-        if (in_dom) {
-            auto* Pm = sm.p0[(i - 1) & 3];
-            auto* Pc = sm.p0[i & 3];
-            auto* Pp = sm.p0[(i + 1) & 3];
-            T p1v;
-            if (interior) {
-                const T pc = Pc[rho][c];
-                const T ss = cell_ss<T>(cur[CA0], cur[CA1], cur[CA2], cur[CA3], cur[CB0], cur[CB1], cur[CB2],
-                                        cur[CC0], cur[CC1], cur[CC2], cur[CBND], cur[CWRK1],
-                                        Pp[rho][c], Pc[rho + 1][c], Pc[rho][c + 1],
-                                        bracket(Pp[rho + 1][c], Pp[rho - 1][c], Pm[rho + 1][c], Pm[rho - 1][c]),
-                                        bracket(Pc[rho + 1][c + 1], Pc[rho - 1][c + 1], Pc[rho + 1][c - 1],
-                                                Pc[rho - 1][c - 1]),
-                                        bracket(Pp[rho][c + 1], Pm[rho][c + 1], Pp[rho][c - 1], Pm[rho][c - 1]),
-                                        Pm[rho][c], Pc[rho - 1][c], Pc[rho][c - 1], pc);
-                p1v = pc + omega * ss;
-                if (out && i >= ib && i < ie) {
-                    const double d = (double)ss;
-                    acc1 += d * d;
-                }
-            } else {
-                p1v = Pc[rho][c];                              // the shell is never updated
-            }
-            sm.p1[i & 3][r1][c1] = p1v;
-        }
-        put(i + 2, pp);
-        __syncthreads();
-
-        // ---- second iteration at plane i-1, own cells
-        const int i2 = i - 1;
-        if (out && i2 >= ib && i2 < ie) {
-            auto* Qm = sm.p1[(i2 - 1) & 3];
-            auto* Qc = sm.p1[i2 & 3];
-            auto* Qp = sm.p1[(i2 + 1) & 3];
-            const T qc = Qc[r1][c1];
-            const T ss = cell_ss<T>(keep[CA0], keep[CA1], keep[CA2], keep[CA3], keep[CB0], keep[CB1], keep[CB2],
-                                    keep[CC0], keep[CC1], keep[CC2], keep[CBND], keep[CWRK1],
-                                    Qp[r1][c1], Qc[r1 + 1][c1], Qc[r1][c1 + 1],
-                                    bracket(Qp[r1 + 1][c1], Qp[r1 - 1][c1], Qm[r1 + 1][c1], Qm[r1 - 1][c1]),
-                                    bracket(Qc[r1 + 1][c1 + 1], Qc[r1 - 1][c1 + 1], Qc[r1 + 1][c1 - 1],
-                                            Qc[r1 - 1][c1 - 1]),
-                                    bracket(Qp[r1][c1 + 1], Qm[r1][c1 + 1], Qp[r1][c1 - 1], Qm[r1][c1 - 1]),
-                                    Qm[r1][c1], Qc[r1 - 1][c1], Qc[r1][c1 - 1], qc);
-            const T outv = qc + omega * ss;
-            T* dst = g.dst + (long long)i2 * g.S + rowoff;
-            if constexpr (NT) __builtin_nontemporal_store(outv, dst);
-            else *dst = outv;
-            const double d = (double)ss;
-            acc2 += d * d;
-        }
-        if constexpr (KEEP) {
-#pragma unroll
-            for (int q = 0; q < NCOEF; ++q) keep[q] = cur[q];
-        }
-    };
-
-    // step number K of each round of NS uses the register sets K, K+PD mod NS
-    auto stepk = [&](auto kc, int i) {
-        constexpr int K = decltype(kc)::value;
-        step(i, cs[K % NS], cs[(K + PD) % NS], ps[(K + PD) % NS], ps[K % NS]);
-    };
-    for (int i = i_lo;;) {
-        stepk(std::integral_constant<int, 0>{}, i);
-        if (++i > i_hi) break;
-        stepk(std::integral_constant<int, 1>{}, i);
-        if (++i > i_hi) break;
-        if constexpr (NS > 2) {
-            stepk(std::integral_constant<int, 2>{}, i);
-            if (++i > i_hi) break;
-        }
-    }
+    if (!t.active) { t.j = j0 - 1; t.k = k0 - 1; }       // an idle lane: the tile's first cell's line
+    return t;
 }
 
-template <typename T, int BJ, bool NT, bool KEEP>
+template <typename T, int BJ, bool NT, bool KEEP, bool PF>
 __device__ __forceinline__ void wide_block(const Grid<T>& g, T omega, int kt, int jt, int ic, int ichunk, int L,
                                            WideLds<T, BJ>& sm, double* __restrict__ part1,
                                            double* __restrict__ part2)
@@ -1055,8 +1097,13 @@ __device__ __forceinline__ void wide_block(const Grid<T>& g, T omega, int kt, in
     int ie = ib + ichunk;
     if (ie > g.nx - 1) ie = g.nx - 1;
     double acc1 = 0.0, acc2 = 0.0;
-    if constexpr (sizeof(T) == 8) wide_tile_sync<T, BJ, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
-    else wide_tile_prefetch<T, BJ, NT, KEEP, 2>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
+    if constexpr (!PF) {
+        wide_tile_sync<T, BJ, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
+    } else {
+        const int k0 = 1 + kt * kWave, j0 = 1 + jt * BJ;
+        tile2_prefetch<T, WideLds<T, BJ>, NT, KEEP, 2>(g, omega, j0, k0, wide_cell<BJ>(j0, k0), ib, ie, sm, acc1,
+                                                       acc2);
+    }
     acc1 = block_sum<BJ + 3>(acc1, sm.red);
     if (threadIdx.x == 0) part1[L] = acc1;
     acc2 = block_sum<BJ + 3>(acc2, sm.red);
@@ -1073,7 +1120,7 @@ __global__ __launch_bounds__(kWave * (BJ + 3)) void wide_kernel(Grid<T> g, T ome
     const int kt = L % kt_n;
     const int jt = (L / kt_n) % jt_n;
     const int ic = L / (kt_n * jt_n);
-    wide_block<T, BJ, NT, KEEP>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
+    wide_block<T, BJ, NT, KEEP, kPrefetchSingle<T>>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
 }
 
 template <typename T, int BJ, bool NT, bool KEEP>
@@ -1096,7 +1143,7 @@ __global__ __launch_bounds__(kWave * (BJ + 3)) void wide_batch_kernel(const Inst
     const int kt = t % d.kt_n;
     const int jt = (t / d.kt_n) % d.jt_n;
     const int ic = t / (d.kt_n * d.jt_n);
-    wide_block<T, BJ, NT, KEEP>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
+    wide_block<T, BJ, NT, KEEP, false>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
 }
 
 // ---- flat kernel: tiles of consecutive interior (j,k) cells -------------------
