@@ -402,12 +402,14 @@ __device__ __forceinline__ T oload(const T* base, unsigned off)
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Which two-iteration tiles prefetch (tile2_prefetch): the FP32 single-solve
-// kernels. FP64 cannot hold the extra register set, and the batch kernels'
-// short chunks of small grids lose more to the deeper prologue and the
-// loads past each chunk's end than they gain (measured: batch64 FP32 -9%).
+// Steps of prefetch of the two-iteration tiles (0: the synchronous tiles;
+// PD > 0: tile2_prefetch): two for the FP32 single-solve kernels. FP64
+// cannot hold the extra register set. The batch kernels keep the synchronous
+// tiles: on batch64 the prefetching one lost 9% (FP32, two steps) and the
+// one-step form 9% (FP32) and 8% (FP64); with small ragged grids more lanes
+// load clamped addresses, and the chunks' prologues and ends weigh more.
 template <typename T>
-constexpr bool kPrefetchSingle = sizeof(T) == 4;
+constexpr int kPrefetchSingle = sizeof(T) == 4 ? 2 : 0;
 
 // A thread's first-iteration cell in a two-iteration tile whose p0 tile
 // starts at (j0-2, k0-2): grid cell (j, k), its place (rho, c) in the p0 tile
@@ -790,7 +792,7 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
 
 // One workgroup's whole share of a two-iteration pass: tile (kt, jt), i-chunk
 // ic, both iterations' gosa partials to slot L of part1 / part2.
-template <typename T, int BJ, int W, bool NT, bool KEEP, bool PF>
+template <typename T, int BJ, int W, bool NT, bool KEEP, int PF>
 __device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, int jt, int ic, int ichunk, int L,
                                             FusedLds<T, BJ, W>& sm, double* __restrict__ part1,
                                             double* __restrict__ part2)
@@ -799,11 +801,11 @@ __device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, i
     int ie = ib + ichunk;
     if (ie > g.nx - 1) ie = g.nx - 1;
     double acc1 = 0.0, acc2 = 0.0;
-    if constexpr (!PF) {
+    if constexpr (PF == 0) {
         fused_tile<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
     } else {
         const int k0 = 1 + kt * FusedLds<T, BJ, W>::TK, j0 = 1 + jt * BJ;
-        tile2_prefetch<T, FusedLds<T, BJ, W>, NT, KEEP, 2>(g, omega, j0, k0, fused_cell<BJ, W>(j0, k0), ib, ie, sm,
+        tile2_prefetch<T, FusedLds<T, BJ, W>, NT, KEEP, PF>(g, omega, j0, k0, fused_cell<BJ, W>(j0, k0), ib, ie, sm,
                                                            acc1, acc2);
     }
     constexpr int NW = FusedLds<T, BJ, W>::NW;
@@ -856,7 +858,7 @@ __global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fu
     const int kt = t % d.kt_n;
     const int jt = (t / d.kt_n) % d.jt_n;
     const int ic = t / (d.kt_n * d.jt_n);
-    fused_block<T, BJ, W, NT, KEEP, false>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
+    fused_block<T, BJ, W, NT, KEEP, 0>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
 }
 
 // ---- wide fused kernel: 64 own cells per row and a halo wave -----------------
@@ -1088,7 +1090,7 @@ __device__ __forceinline__ TileCell wide_cell(int j0, int k0)
     return t;
 }
 
-template <typename T, int BJ, bool NT, bool KEEP, bool PF>
+template <typename T, int BJ, bool NT, bool KEEP, int PF>
 __device__ __forceinline__ void wide_block(const Grid<T>& g, T omega, int kt, int jt, int ic, int ichunk, int L,
                                            WideLds<T, BJ>& sm, double* __restrict__ part1,
                                            double* __restrict__ part2)
@@ -1097,11 +1099,11 @@ __device__ __forceinline__ void wide_block(const Grid<T>& g, T omega, int kt, in
     int ie = ib + ichunk;
     if (ie > g.nx - 1) ie = g.nx - 1;
     double acc1 = 0.0, acc2 = 0.0;
-    if constexpr (!PF) {
+    if constexpr (PF == 0) {
         wide_tile_sync<T, BJ, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
     } else {
         const int k0 = 1 + kt * kWave, j0 = 1 + jt * BJ;
-        tile2_prefetch<T, WideLds<T, BJ>, NT, KEEP, 2>(g, omega, j0, k0, wide_cell<BJ>(j0, k0), ib, ie, sm, acc1,
+        tile2_prefetch<T, WideLds<T, BJ>, NT, KEEP, PF>(g, omega, j0, k0, wide_cell<BJ>(j0, k0), ib, ie, sm, acc1,
                                                        acc2);
     }
     acc1 = block_sum<BJ + 3>(acc1, sm.red);
@@ -1143,7 +1145,7 @@ __global__ __launch_bounds__(kWave * (BJ + 3)) void wide_batch_kernel(const Inst
     const int kt = t % d.kt_n;
     const int jt = (t / d.kt_n) % d.jt_n;
     const int ic = t / (d.kt_n * d.jt_n);
-    wide_block<T, BJ, NT, KEEP, false>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
+    wide_block<T, BJ, NT, KEEP, 0>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
 }
 
 // ---- flat kernel: tiles of consecutive interior (j,k) cells -------------------
