@@ -293,17 +293,19 @@ def transfer_ablation(w, hj, arrays):
     from paper_2002_12115_amd import transfer
     out = {}
     ref = None
-    for policy, n in (("resident", w.iters), ("p_every_k", w.iters), ("p_every_iter", 20),
-                      ("all_every_iter", 10)):
+    for policy, n, pinned in (("resident", w.iters, False), ("p_every_k", w.iters, False),
+                              ("p_every_iter", 20, False), ("all_every_iter", 10, False),
+                              ("p_every_k", w.iters, True), ("p_every_iter", 20, True),
+                              ("all_every_iter", 10, True)):
         s = hj.Solver(w.dtype, w.shape)
-        r = transfer.run(s, arrays, policy, n, w.omega, k=10)
+        r = transfer.run(s, arrays, policy, n, w.omega, k=10, pinned=pinned)
         s.close()
         if policy == "resident":
             ref = r
         same = None
         if n == ref["iters"]:
             same = bool(np.array_equal(r["field"], ref["field"]))
-        out[policy] = {"glups": interior(w.shape) * n / r["wall_s"] / 1e9, "iters": n, "k": r["k"],
+        out[policy + ("_pinned" if pinned else "")] = {"glups": interior(w.shape) * n / r["wall_s"] / 1e9, "iters": n, "k": r["k"],
                        "ms_per_iter": r["wall_s"] * 1e3 / n,
                        "pcie_gbps": (r["h2d_bytes"] + r["d2h_bytes"]) / r["wall_s"] / 1e9,
                        "field_equals_resident": same}

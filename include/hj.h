@@ -125,13 +125,17 @@ int hj_attach(hj_solver* out, int dtype, int nx, int ny, int nz, void* device_sl
 /* Upload one input field from a dense host array in the handle's dtype
  * (hj_upload) or in FP64 (hj_upload_f64, rounded to nearest even for HJ_F32
  * handles). Uploading HJ_P also resets the ping-pong partner to p and makes
- * p current. HJ_WRK2 cannot be uploaded (HJ_ERR_ARG). Synchronous. */
+ * p current. HJ_WRK2 cannot be uploaded (HJ_ERR_ARG). Synchronous. A pinned
+ * host array (hipHostMalloc, a torch pin_memory tensor) is copied directly;
+ * a pageable one is staged through the library's pinned buffers (one host
+ * copy more), as is any FP64 source of an HJ_F32 handle. */
 int hj_upload(hj_solver h, int field, const void* host_src);
 int hj_upload_f64(hj_solver h, int field, const double* host_src);
 
 /* Download a field into a dense host array of the handle's dtype. HJ_P and
  * HJ_WRK2 both return the current field (the last sweep's wrk2 once any
- * sweep has run). Synchronous. */
+ * sweep has run). Synchronous. Pinned host memory is written directly, as
+ * for hj_upload. */
 int hj_download(hj_solver h, int field, void* host_dst);
 
 /* Run n_iter Jacobi iterations with relaxation omega on the resident arrays.

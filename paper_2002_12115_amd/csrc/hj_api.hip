@@ -863,11 +863,11 @@ int solver_init(hj_solver* out, int dtype, int nx, int ny, int nz, void* dev_sla
     return HJ_OK;
 }
 
-// Host <-> device copies of one dense field.
 // Host <-> device copies of one dense field. They go through two pinned
 // staging buffers shared by the process, so the PCIe transfer of one chunk of
 // rows overlaps the host-side copy (or FP64 -> FP32 rounding) of the next.
-// Rows too long for a staging buffer take a direct pitched copy.
+// Rows too long for a staging buffer, and host arrays that are pinned
+// already, take a direct pitched copy.
 struct Stager {
     static constexpr size_t kBytes = 32u << 20;
     std::mutex mu;
@@ -893,6 +893,18 @@ void round_rows(float* dst, const double* src, size_t n)
     for (size_t q = 0; q < n; ++q) dst[q] = (float)src[q];  // round to nearest even
 }
 
+// True when host memory p is pinned (hipHostMalloc, or a torch pin_memory
+// tensor): a DMA copy can then read or write it directly, with no staging.
+bool host_pinned(const void* p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // pageable memory is not an error here
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
+
 // src holds nx*ny rows of nz values: doubles when src_f64, else the field's type.
 void copy_in(const Layout& L, char* field, const void* src, bool src_f64, hipStream_t st)
 {
@@ -900,7 +912,7 @@ void copy_in(const Layout& L, char* field, const void* src, bool src_f64, hipStr
     const size_t row = (size_t)L.nz * L.esz, pitch = (size_t)L.P * L.esz;
     const size_t rows = (size_t)L.nx * L.ny;
     const bool convert = src_f64 && L.esz == 4;
-    if (row > Stager::kBytes) {
+    if (row > Stager::kBytes || (!convert && host_pinned(src))) {
         std::vector<float> tmp;
         const void* s = src;
         if (convert) {
@@ -937,7 +949,7 @@ void copy_out(const Layout& L, const char* field, void* dst, hipStream_t st)
     const char* src = field + (size_t)(L.A - 1) * L.esz;
     const size_t row = (size_t)L.nz * L.esz, pitch = (size_t)L.P * L.esz;
     const size_t rows = (size_t)L.nx * L.ny;
-    if (row > Stager::kBytes) {
+    if (row > Stager::kBytes || host_pinned(dst)) {
         HIPCHK(hipMemcpy2DAsync(dst, row, src, pitch, row, rows, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         return;

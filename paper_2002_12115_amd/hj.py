@@ -207,8 +207,13 @@ class Solver:
         for n in INPUTS:
             self.upload(n, arrays[n])
 
-    def download(self, name="p") -> np.ndarray:
-        out = np.empty(self.shape, dtype=self.np_dtype)
+    def download(self, name="p", out: Optional[np.ndarray] = None) -> np.ndarray:
+        """The field as a new array, or written into `out` (C-contiguous, the
+        solver's shape and dtype; a pinned buffer is copied to directly)."""
+        if out is None:
+            out = np.empty(self.shape, dtype=self.np_dtype)
+        elif out.shape != self.shape or out.dtype != self.np_dtype or not out.flags.c_contiguous:
+            raise ValueError("out must be a C-contiguous %s array of shape %s" % (self.np_dtype, self.shape))
         check(self.lib.hj_download(self._h, _field(name), out.ctypes.data), "hj_download(%s)" % (name,))
         return out
 

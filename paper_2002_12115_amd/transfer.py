@@ -16,6 +16,11 @@ Placements:
   all_every_iter    all 13 inputs are uploaded before every iteration and the
                     field is downloaded after it (per-loop offload with no
                     data region)
+
+With pinned=True the host side of every transfer is pinned memory (copies
+of the inputs made before the timed region), which the library copies to
+and from directly; otherwise ordinary (pageable) arrays, which it stages
+through its own pinned buffers.
 """
 from __future__ import annotations
 
@@ -29,8 +34,18 @@ from .inputs import INPUTS
 POLICIES = ("resident", "p_every_k", "p_every_iter", "all_every_iter")
 
 
+def pinned_like(a: np.ndarray, dtype=None) -> np.ndarray:
+    """A copy of `a` in pinned host memory (allocated through torch)."""
+    import torch
+    dt = np.dtype(dtype or a.dtype)
+    t = torch.empty(a.shape, dtype=torch.float64 if dt == np.float64 else torch.float32, pin_memory=True)
+    out = t.numpy()
+    out[...] = a
+    return out
+
+
 def run(solver, arrays: Mapping[str, np.ndarray], policy: str, n_iter: int, omega: float,
-        k: int = 10) -> Dict[str, object]:
+        k: int = 10, pinned: bool = False) -> Dict[str, object]:
     """Upload `arrays`, run n_iter iterations under `policy`, return timings,
     bytes moved, the final field and the gosa history."""
     if policy not in POLICIES:
@@ -38,8 +53,13 @@ def run(solver, arrays: Mapping[str, np.ndarray], policy: str, n_iter: int, omeg
     esz = np.dtype(solver.np_dtype).itemsize
     cells = int(np.prod(solver.shape))
     field_bytes = cells * esz
+    if pinned:   # the inputs in the solver's dtype, pinned, before the timed region
+        arrays = {n: pinned_like(arrays[n], solver.np_dtype) for n in INPUTS}
     solver.upload_all(arrays)
-    host = np.array(solver.download("p"))           # the host's copy of the field
+    if pinned:
+        host = solver.download("p", out=pinned_like(arrays["p"]))   # the host's copy of the field
+    else:
+        host = np.array(solver.download("p"))
     h2d = d2h = 0
     hist = []
     t0 = time.perf_counter()
@@ -57,7 +77,7 @@ def run(solver, arrays: Mapping[str, np.ndarray], policy: str, n_iter: int, omeg
                 h2d += len(INPUTS) * field_bytes
             solver.sweep(n, omega)
             hist.extend(solver.gosa_history)
-            host = solver.download("p")
+            host = solver.download("p", out=host if pinned else None)
             d2h += field_bytes
             if policy != "all_every_iter":
                 solver.upload("p", host)
@@ -65,6 +85,6 @@ def run(solver, arrays: Mapping[str, np.ndarray], policy: str, n_iter: int, omeg
             done += n
     wall = time.perf_counter() - t0
     final = solver.download("p")
-    return {"policy": policy, "iters": n_iter, "k": k if policy == "p_every_k" else None,
+    return {"policy": policy, "pinned": pinned, "iters": n_iter, "k": k if policy == "p_every_k" else None,
             "wall_s": wall, "h2d_bytes": h2d, "d2h_bytes": d2h, "field": final,
             "gosa_history": np.asarray(hist)}

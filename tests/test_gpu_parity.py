@@ -349,6 +349,40 @@ def test_transfer_placements_give_the_same_solve(dtype):
         assert np.array_equal(ref["field"], pref)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pinned_host_buffers_match_pageable(dtype):
+    """Uploads from and downloads into pinned host memory (copied directly,
+    without the library's staging buffers) give the same arrays, the same
+    solve and the same transfer placements as pageable arrays."""
+    from paper_2002_12115_amd import transfer
+    shape = (21, 34, 70)
+    f = inputs.fields(9, shape)
+    say("pinned buffers", dtype)
+    with hj.Solver(dtype, shape) as s:
+        pin = {n: transfer.pinned_like(f[n], s.np_dtype) for n in inputs.INPUTS}
+        s.upload_all(pin)
+        for n in inputs.INPUTS:
+            out = s.download(n, out=transfer.pinned_like(np.zeros(shape), s.np_dtype))
+            assert np.array_equal(out, f[n].astype(s.np_dtype)), n
+        s.sweep(5, 0.8)
+        p_pin = s.download("p", out=transfer.pinned_like(np.zeros(shape), s.np_dtype))
+        assert np.array_equal(p_pin, s.download("p"))
+        with pytest.raises(ValueError):
+            s.download("p", out=np.zeros((3, 3, 3), dtype=s.np_dtype))
+    with hj.Solver(dtype, shape) as s:
+        s.upload_all(f)
+        s.sweep(5, 0.8)
+        assert np.array_equal(s.download("p"), p_pin)
+    runs = {}
+    for pinned in (False, True):
+        with hj.Solver(dtype, shape) as s:
+            runs[pinned] = transfer.run(s, f, "p_every_iter", 6, 0.8, pinned=pinned)
+    assert np.array_equal(runs[True]["field"], runs[False]["field"])
+    assert np.array_equal(runs[True]["gosa_history"], runs[False]["gosa_history"])
+    if dtype == "f64":
+        assert np.array_equal(runs[True]["field"], oracle.sweep(f, 6, 0.8)[0])
+
+
 def test_flat_fit_is_enforced():
     """A flat run too wide for the grid is refused, never launched."""
     # FP64 staged plane: 1280 values. nz = 300: runs of 128 cells touch 4 rows
