@@ -22,6 +22,7 @@
 #include <new>
 #include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hj_ga.hpp"
@@ -888,9 +889,37 @@ Stager& stager()
     return *s;
 }
 
+// Runs f(begin, end) over [0, n) split across up to 8 host threads (one
+// thread copies pageable memory at about 10 GB/s, well under the PCIe link).
+template <typename F>
+void host_parallel(size_t n, size_t min_per_thread, F f)
+{
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t t = std::min<size_t>({8, hw, std::max<size_t>(1, n / min_per_thread)});
+    if (t < 2) {
+        f(size_t(0), n);
+        return;
+    }
+    const size_t per = (n + t - 1) / t;
+    std::vector<std::thread> th;
+    th.reserve(t - 1);
+    for (size_t i = 1; i < t && i * per < n; ++i) th.emplace_back(f, i * per, std::min(n, (i + 1) * per));
+    f(size_t(0), std::min(n, per));
+    for (std::thread& x : th) x.join();
+}
+
+void par_memcpy(void* dst, const void* src, size_t bytes)
+{
+    host_parallel(bytes, size_t(4) << 20, [=](size_t b, size_t e) {
+        memcpy(static_cast<char*>(dst) + b, static_cast<const char*>(src) + b, e - b);
+    });
+}
+
 void round_rows(float* dst, const double* src, size_t n)
 {
-    for (size_t q = 0; q < n; ++q) dst[q] = (float)src[q];  // round to nearest even
+    host_parallel(n, size_t(1) << 20, [=](size_t b, size_t e) {
+        for (size_t q = b; q < e; ++q) dst[q] = (float)src[q];  // round to nearest even
+    });
 }
 
 // True when host memory p is pinned (hipHostMalloc, or a torch pin_memory
@@ -936,7 +965,7 @@ void copy_in(const Layout& L, char* field, const void* src, bool src_f64, hipStr
         if (convert)
             round_rows(static_cast<float*>(sg.buf[b]), static_cast<const double*>(src) + r0 * L.nz, n * L.nz);
         else
-            memcpy(sg.buf[b], static_cast<const char*>(src) + r0 * row, n * row);
+            par_memcpy(sg.buf[b], static_cast<const char*>(src) + r0 * row, n * row);
         HIPCHK(hipMemcpy2DAsync(dst + r0 * pitch, pitch, sg.buf[b], row, row, n, hipMemcpyHostToDevice, st));
         HIPCHK(hipEventRecord(sg.ev[b], st));
         used[b] = true;
@@ -966,14 +995,14 @@ void copy_out(const Layout& L, const char* field, void* dst, hipStream_t st)
         HIPCHK(hipEventRecord(sg.ev[b], st));
         if (prev_n) {  // drain the other buffer while this chunk is in flight
             HIPCHK(hipEventSynchronize(sg.ev[b ^ 1]));
-            memcpy(static_cast<char*>(dst) + prev_r0 * row, sg.buf[b ^ 1], prev_n * row);
+            par_memcpy(static_cast<char*>(dst) + prev_r0 * row, sg.buf[b ^ 1], prev_n * row);
         }
         prev_r0 = r0;
         prev_n = n;
     }
     if (prev_n) {
         HIPCHK(hipEventSynchronize(sg.ev[b ^ 1]));
-        memcpy(static_cast<char*>(dst) + prev_r0 * row, sg.buf[b ^ 1], prev_n * row);
+        par_memcpy(static_cast<char*>(dst) + prev_r0 * row, sg.buf[b ^ 1], prev_n * row);
     }
     HIPCHK(hipStreamSynchronize(st));
 }
