@@ -296,7 +296,8 @@ def transfer_ablation(w, hj, arrays):
     for policy, n, pinned in (("resident", w.iters, False), ("p_every_k", w.iters, False),
                               ("p_every_iter", 20, False), ("all_every_iter", 10, False),
                               ("p_every_k", w.iters, True), ("p_every_iter", 20, True),
-                              ("all_every_iter", 10, True)):
+                              ("all_every_iter", 10, True), ("observe_every_k", w.iters, True),
+                              ("observe_every_k_async", w.iters, True)):
         s = hj.Solver(w.dtype, w.shape)
         r = transfer.run(s, arrays, policy, n, w.omega, k=10, pinned=pinned)
         s.close()

@@ -138,6 +138,23 @@ int hj_upload_f64(hj_solver h, int field, const double* host_src);
  * for hj_upload. */
 int hj_download(hj_solver h, int field, void* host_dst);
 
+/* Send the current field to the host while later work proceeds: enqueues,
+ * on the handle's stream, a dense copy of p into a device buffer the handle
+ * owns (allocated at the first call, nx*ny*nz elements), then the copy of that buffer
+ * to host_dst (a dense host array of the handle's dtype) on a second stream
+ * of the handle. Returns without waiting: sweeps enqueued afterwards run
+ * while the transfer proceeds. host_dst must stay valid, and unread, until
+ * hj_snapshot_wait; the transfer overlaps only if host_dst is pinned. A
+ * further snapshot is ordered after the previous one's transfer. This is the
+ * overlapped form of observing the field every k iterations: a transfer the
+ * paper's section 3.3 would hoist out of the loop, when the host needs the
+ * field inside it. */
+int hj_snapshot(hj_solver h, void* host_dst);
+
+/* Wait until the last hj_snapshot's host array is written. HJ_OK with none
+ * pending. hj_destroy also waits. */
+int hj_snapshot_wait(hj_solver h);
+
 /* Run n_iter Jacobi iterations with relaxation omega on the resident arrays.
  * gosa_last (nullable) receives the last iteration's gosa, gosa_hist
  * (nullable, n_iter doubles) every iteration's, each computed from the field

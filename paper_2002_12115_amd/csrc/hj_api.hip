@@ -691,6 +691,11 @@ struct hj_solver_s {
     PinBuf host_gosa;
     GraphCache graphs;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // hj_snapshot: a dense device copy of p, sent to the host on a stream of its own
+    DevBuf snap;
+    hipStream_t xfer = nullptr;
+    hipEvent_t snap_ready = nullptr, snap_sent = nullptr;
+    bool snap_pending = false;
 
     char* field(int q) const { return slab + (size_t)q * L.field_stride; }
     // element (0,0,0) of field q
@@ -1257,6 +1262,44 @@ int hj_download(hj_solver h, int field, void* dst)
     });
 }
 
+int hj_snapshot(hj_solver h, void* host_dst)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (!host_dst) return set_err(HJ_ERR_ARG, "host_dst is NULL");
+    return guarded([&]() -> int {
+        const Layout& L = h->L;
+        const size_t row = (size_t)L.nz * L.esz, pitch = (size_t)L.P * L.esz, rows = (size_t)L.nx * L.ny;
+        if (!h->xfer) {
+            h->snap.ensure(rows * row);
+            stream_create(&h->xfer);
+            HIPCHK(hipEventCreateWithFlags(&h->snap_ready, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&h->snap_sent, hipEventDisableTiming));
+        }
+        // the previous snapshot's transfer must have read the buffer first
+        if (h->snap_pending) HIPCHK(hipStreamWaitEvent(h->stream, h->snap_sent, 0));
+        // the field, made dense on the device (fast), then one flat copy over
+        // PCIe (a pitched host copy of short rows runs well below the link)
+        const char* cur = h->field(h->parity ? HJ_WRK2 : HJ_P) + (size_t)(L.A - 1) * L.esz;
+        HIPCHK(hipMemcpy2DAsync(h->snap.p, row, cur, pitch, row, rows, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipEventRecord(h->snap_ready, h->stream));
+        HIPCHK(hipStreamWaitEvent(h->xfer, h->snap_ready, 0));
+        HIPCHK(hipMemcpyAsync(host_dst, h->snap.p, rows * row, hipMemcpyDeviceToHost, h->xfer));
+        HIPCHK(hipEventRecord(h->snap_sent, h->xfer));
+        h->snap_pending = true;
+        return HJ_OK;
+    });
+}
+
+int hj_snapshot_wait(hj_solver h)
+{
+    if (int rc = check_solver(h)) return rc;
+    return guarded([&]() -> int {
+        if (h->snap_pending) HIPCHK(hipEventSynchronize(h->snap_sent));
+        h->snap_pending = false;
+        return HJ_OK;
+    });
+}
+
 int hj_sweep(hj_solver h, int n_iter, double omega, double* gosa_last, double* gosa_hist)
 {
     if (int rc = check_solver(h)) return rc;
@@ -1496,6 +1539,13 @@ int hj_destroy(hj_solver h)
     if (int rc = check_solver(h)) return rc;
     reg_del(h);
     (void)hipStreamSynchronize(h->stream);
+    if (h->xfer) {
+        (void)hipStreamSynchronize(h->xfer);
+        stream_destroy(h->xfer);
+        (void)hipEventDestroy(h->snap_ready);
+        (void)hipEventDestroy(h->snap_sent);
+    }
+    h->snap.release();
     h->graphs.clear();
     h->part.release();
     h->gosa.release();

@@ -80,6 +80,8 @@ def load() -> ctypes.CDLL:
         "hj_upload": [H, i32, vp],
         "hj_upload_f64": [H, i32, vp],
         "hj_download": [H, i32, vp],
+        "hj_snapshot": [H, vp],
+        "hj_snapshot_wait": [H],
         "hj_sweep": [H, i32, dbl, dp, dp],
         "hj_sweep_async": [H, i32, dbl, vp],
         "hj_residual": [H, dp],
@@ -189,6 +191,7 @@ class Solver:
         else:
             check(self.lib.hj_create(ctypes.byref(self._h), self.dtype, nx, ny, nz, st), "hj_create")
         self.gosa_history: Optional[np.ndarray] = None
+        self._snap: Optional[np.ndarray] = None
         self.last_ms: float = 0.0
 
     # -- data movement --
@@ -216,6 +219,19 @@ class Solver:
             raise ValueError("out must be a C-contiguous %s array of shape %s" % (self.np_dtype, self.shape))
         check(self.lib.hj_download(self._h, _field(name), out.ctypes.data), "hj_download(%s)" % (name,))
         return out
+
+    def snapshot(self, out: np.ndarray) -> None:
+        """Start sending the current field to `out` (C-contiguous, the
+        solver's shape and dtype; pinned for the transfer to overlap later
+        sweeps). `out` must stay untouched until snapshot_wait()."""
+        if out.shape != self.shape or out.dtype != self.np_dtype or not out.flags.c_contiguous:
+            raise ValueError("out must be a C-contiguous %s array of shape %s" % (self.np_dtype, self.shape))
+        self._snap = out          # keep the array alive while the copy runs
+        check(self.lib.hj_snapshot(self._h, out.ctypes.data), "hj_snapshot")
+
+    def snapshot_wait(self) -> None:
+        check(self.lib.hj_snapshot_wait(self._h), "hj_snapshot_wait")
+        self._snap = None
 
     # -- compute --
     def sweep(self, n_iter: int, omega: float) -> float:
@@ -291,9 +307,10 @@ class Solver:
 
     def close(self) -> None:
         if self._h:
-            check(self.lib.hj_destroy(self._h), "hj_destroy")
+            check(self.lib.hj_destroy(self._h), "hj_destroy")   # waits for a pending snapshot
             self._h = ctypes.c_void_p()
         self._slab = None
+        self._snap = None
 
     def __enter__(self):
         return self

@@ -16,6 +16,9 @@ Placements:
   all_every_iter    all 13 inputs are uploaded before every iteration and the
                     field is downloaded after it (per-loop offload with no
                     data region)
+  observe_every_k   the host reads the field every k iterations (no upload)
+  observe_every_k_async   the same reads, each sent by hj_snapshot while the
+                    next k iterations run (overlapped; pinned host arrays)
 
 With pinned=True the host side of every transfer is pinned memory (copies
 of the inputs made before the timed region), which the library copies to
@@ -31,7 +34,8 @@ import numpy as np
 
 from .inputs import INPUTS
 
-POLICIES = ("resident", "p_every_k", "p_every_iter", "all_every_iter")
+POLICIES = ("resident", "p_every_k", "p_every_iter", "all_every_iter", "observe_every_k",
+            "observe_every_k_async")
 
 
 def pinned_like(a: np.ndarray, dtype=None) -> np.ndarray:
@@ -62,10 +66,33 @@ def run(solver, arrays: Mapping[str, np.ndarray], policy: str, n_iter: int, omeg
         host = np.array(solver.download("p"))
     h2d = d2h = 0
     hist = []
+    # observe placements: two host arrays, so the host may read one while the
+    # other is written (allocated here, outside the timed region)
+    spare = None
+    if policy.startswith("observe_every_k"):
+        spare = pinned_like(host) if pinned else np.empty_like(host)
     t0 = time.perf_counter()
     if policy == "resident":
         solver.sweep(n_iter, omega)
         hist.extend(solver.gosa_history)
+    elif policy.startswith("observe_every_k"):
+        overlap = policy.endswith("_async")
+        views = [host, spare]
+        done = 0
+        while done < n_iter:
+            n = min(k, n_iter - done)
+            solver.sweep(n, omega)
+            hist.extend(solver.gosa_history)
+            done += n
+            dst = views[(done // k) % 2]
+            if overlap:
+                solver.snapshot_wait()          # the previous snapshot's array is complete
+                solver.snapshot(dst)
+            else:
+                solver.download("p", out=dst)
+            d2h += field_bytes
+        if overlap:
+            solver.snapshot_wait()
     else:
         step = k if policy == "p_every_k" else 1
         done = 0

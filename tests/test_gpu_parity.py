@@ -383,6 +383,47 @@ def test_pinned_host_buffers_match_pageable(dtype):
         assert np.array_equal(runs[True]["field"], oracle.sweep(f, 6, 0.8)[0])
 
 
+def test_snapshots_equal_the_field_when_taken():
+    """hj_snapshot sends the field as it stands when called, while later
+    sweeps run; pageable targets work too, and destroying a handle with a
+    snapshot in flight waits for it. The observe placements (synchronous and
+    overlapped) give the resident field."""
+    from paper_2002_12115_amd import transfer
+    shape = (30, 33, 100)
+    f = inputs.fields(11, shape)
+    say("snapshots")
+    snaps, done = [], 0
+    with hj.Solver("f64", shape) as s:
+        s.upload_all(f)
+        for n in (1, 2, 3):
+            s.sweep(n, 0.8)
+            done += n
+            snap = transfer.pinned_like(np.zeros(shape))
+            s.snapshot(snap)
+            s.sweep(2, 0.8)                      # runs while the snapshot is sent
+            snaps.append((done, snap))
+            done += 2
+            s.snapshot_wait()
+        final = s.download()
+        pageable = np.zeros(shape)
+        s.snapshot(pageable)
+        s.snapshot_wait()
+        assert np.array_equal(pageable, final)
+        with pytest.raises(ValueError):
+            s.snapshot(np.zeros((3, 3, 3)))
+        s.snapshot(transfer.pinned_like(np.zeros(shape)))   # still in flight at destroy
+    for n_done, snap in snaps:
+        assert np.array_equal(snap, oracle.sweep(f, n_done, 0.8)[0]), n_done
+    assert np.array_equal(final, oracle.sweep(f, done, 0.8)[0])
+    res = {}
+    for policy in ("resident", "observe_every_k", "observe_every_k_async"):
+        with hj.Solver("f64", shape) as s:
+            res[policy] = transfer.run(s, f, policy, 13, 0.8, k=4, pinned=True)
+    for policy in ("observe_every_k", "observe_every_k_async"):
+        assert np.array_equal(res[policy]["field"], res["resident"]["field"]), policy
+        assert res[policy]["d2h_bytes"] == 4 * f["p"].size * 8
+
+
 def test_flat_fit_is_enforced():
     """A flat run too wide for the grid is refused, never launched."""
     # FP64 staged plane: 1280 values. nz = 300: runs of 128 cells touch 4 rows
