@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -41,11 +42,22 @@ def log(*a):
     print("[bench +%.1fs]" % (time.perf_counter() - _T0), *a, file=sys.stderr, flush=True)
 
 
+_CPP_TOKENS = re.compile(r'"(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\'|//[^\n]*|/\*.*?\*/', re.S)
+
+
+def code_only(src: str) -> str:
+    """C++ source without its comments, whitespace runs collapsed: edits to
+    comments or layout do not change it."""
+    kept = _CPP_TOKENS.sub(lambda m: m.group(0) if m.group(0)[0] in "\"'" else " ", src)
+    return " ".join(kept.split())
+
+
 def kernel_hash() -> str:
+    """Identity of the kernel code the stored counter figures were taken on."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
