@@ -138,7 +138,23 @@ def cpu_baseline(w, arrays, budget_s: float):
     return {"value": interior(w.shape) * iters * solves / dt / 1e9, "unit": "GLUPS", "cores": nthreads,
             "kind": "oracle",
             "sample": "%s grid %s, %d x %d of %d iterations, FP64, %d OpenMP threads, %.1f s"
-                      % (w.name, "x".join(map(str, w.shape)), solves, iters, w.iters, nthreads, dt)}
+                      % (w.name, "x".join(map(str, w.shape)), solves, iters, w.iters, nthreads, dt),
+            "host": host_cpu()}
+
+
+def host_cpu() -> dict:
+    """The host the oracle ran on: CPU model, logical CPUs, CPUs this process may use."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def accuracy(w, arrays, p_gpu, hist_gpu, iters: int):
