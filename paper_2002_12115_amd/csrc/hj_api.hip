@@ -1269,12 +1269,11 @@ int hj_snapshot(hj_solver h, void* host_dst)
     return guarded([&]() -> int {
         const Layout& L = h->L;
         const size_t row = (size_t)L.nz * L.esz, pitch = (size_t)L.P * L.esz, rows = (size_t)L.nx * L.ny;
-        if (!h->xfer) {
-            h->snap.ensure(rows * row);
-            stream_create(&h->xfer);
-            HIPCHK(hipEventCreateWithFlags(&h->snap_ready, hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&h->snap_sent, hipEventDisableTiming));
-        }
+        // each resource is made once; a failure part way leaves the rest to the next call
+        if (!h->snap_ready) HIPCHK(hipEventCreateWithFlags(&h->snap_ready, hipEventDisableTiming));
+        if (!h->snap_sent) HIPCHK(hipEventCreateWithFlags(&h->snap_sent, hipEventDisableTiming));
+        if (!h->xfer) stream_create(&h->xfer);
+        h->snap.ensure(rows * row);
         // the previous snapshot's transfer must have read the buffer first
         if (h->snap_pending) HIPCHK(hipStreamWaitEvent(h->stream, h->snap_sent, 0));
         // the field, made dense on the device (fast), then one flat copy over
@@ -1542,9 +1541,9 @@ int hj_destroy(hj_solver h)
     if (h->xfer) {
         (void)hipStreamSynchronize(h->xfer);
         stream_destroy(h->xfer);
-        (void)hipEventDestroy(h->snap_ready);
-        (void)hipEventDestroy(h->snap_sent);
     }
+    if (h->snap_ready) (void)hipEventDestroy(h->snap_ready);
+    if (h->snap_sent) (void)hipEventDestroy(h->snap_sent);
     h->snap.release();
     h->graphs.clear();
     h->part.release();
