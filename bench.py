@@ -476,6 +476,9 @@ def main():
             raise SystemExit("the main line is a single solve; batch64 is reported under extra "
                              "(or run it alone with --profile)")
         r = run_batch(args, hj, inputs, args.batch_dtype, w.iters, False, args.retune)
+        if args.copy_probe:          # the counters' calibration leg, as for single solves
+            ms = hj.copy_probe(args.copy_probe)
+            log("copy probe: %d bytes in %.3f ms" % (args.copy_probe, ms))
         print(json.dumps({"workload": w.name, "batch64_%s_batched" % args.batch_dtype: r}), flush=True)
         return
     if args.profile:
