@@ -85,7 +85,9 @@ enum hj_field {
  * wave computing the halo columns (bj 2, 4, 6, 8 or 12; bj+3 waves); 4,
  * tiles of 30-cell rows, two 32-lane rows per wave (bj 6, 14, 22 or 30;
  * (bj+2)/2 waves). An odd remainder runs one single-iteration launch. 0
- * means 1. The results are bitwise those of tsteps 1.
+ * means 1. The results are bitwise those of tsteps 1. In FP32 these kernels
+ * address a plane with 32-bit byte offsets, so they refuse (HJ_ERR_ARG) a
+ * grid whose plane (ny rows of the padded k pitch) holds 4 GiB or more.
  * reread (tsteps 2 only): 0 holds each cell's coefficients in registers
  * between its two iterations, 1 reads them again for the second (an L2 hit
  * when nontemporal is 0), which frees registers for more resident waves. */
