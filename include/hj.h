@@ -130,7 +130,8 @@ int hj_attach(hj_solver* out, int dtype, int nx, int ny, int nz, void* device_sl
  * p current. HJ_WRK2 cannot be uploaded (HJ_ERR_ARG). Synchronous. A pinned
  * host array (hipHostMalloc, a torch pin_memory tensor) is copied directly;
  * a pageable one is staged through the library's pinned buffers (one host
- * copy more), as is any FP64 source of an HJ_F32 handle. */
+ * copy more), as is any FP64 source of an HJ_F32 handle. A device pointer
+ * is refused (HJ_ERR_ARG), here and wherever the ABI takes a host array. */
 int hj_upload(hj_solver h, int field, const void* host_src);
 int hj_upload_f64(hj_solver h, int field, const double* host_src);
 

@@ -927,17 +927,25 @@ void round_rows(float* dst, const double* src, size_t n)
     });
 }
 
-// True when host memory p is pinned (hipHostMalloc, or a torch pin_memory
-// tensor): a DMA copy can then read or write it directly, with no staging.
-bool host_pinned(const void* p)
+// What a host-side array argument points to: ordinary (pageable) memory;
+// pinned host memory (hipHostMalloc, or a torch pin_memory tensor), which a
+// DMA copy reads or writes directly with no staging; or device memory,
+// which is not a host array.
+enum class HostMem { pageable, pinned, device };
+
+HostMem host_mem(const void* p)
 {
     hipPointerAttribute_t a;
     if (hipPointerGetAttributes(&a, p) != hipSuccess) {
         (void)hipGetLastError();  // pageable memory is not an error here
-        return false;
+        return HostMem::pageable;
     }
-    return a.type == hipMemoryTypeHost;
+    if (a.type == hipMemoryTypeHost) return HostMem::pinned;
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeArray) return HostMem::device;
+    return HostMem::pageable;  // managed memory: reachable from the host
 }
+
+bool host_pinned(const void* p) { return host_mem(p) == HostMem::pinned; }
 
 // src holds nx*ny rows of nz values: doubles when src_f64, else the field's type.
 void copy_in(const Layout& L, char* field, const void* src, bool src_f64, hipStream_t st)
@@ -1228,6 +1236,7 @@ int solver_upload(hj_solver h, int field, const void* src, bool src_f64)
 {
     if (int rc = check_solver(h)) return rc;
     if (!src) return set_err(HJ_ERR_ARG, "host_src is NULL");
+    if (host_mem(src) == HostMem::device) return set_err(HJ_ERR_ARG, "host_src is device memory, not a host array");
     if (field == HJ_WRK2) return set_err(HJ_ERR_ARG, "HJ_WRK2 is derived from HJ_P and cannot be uploaded");
     if (field < 0 || field >= HJ_WRK2) return set_err(HJ_ERR_ARG, "field %d out of range", field);
     return guarded([&]() -> int {
@@ -1253,6 +1262,7 @@ int hj_download(hj_solver h, int field, void* dst)
 {
     if (int rc = check_solver(h)) return rc;
     if (!dst) return set_err(HJ_ERR_ARG, "host_dst is NULL");
+    if (host_mem(dst) == HostMem::device) return set_err(HJ_ERR_ARG, "host_dst is device memory, not a host array");
     if (field < 0 || field >= HJ_NFIELDS) return set_err(HJ_ERR_ARG, "field %d out of range", field);
     return guarded([&]() -> int {
         int q = field;
@@ -1266,6 +1276,8 @@ int hj_snapshot(hj_solver h, void* host_dst)
 {
     if (int rc = check_solver(h)) return rc;
     if (!host_dst) return set_err(HJ_ERR_ARG, "host_dst is NULL");
+    if (host_mem(host_dst) == HostMem::device)
+        return set_err(HJ_ERR_ARG, "host_dst is device memory, not a host array");
     return guarded([&]() -> int {
         const Layout& L = h->L;
         const size_t row = (size_t)L.nz * L.esz, pitch = (size_t)L.P * L.esz, rows = (size_t)L.nx * L.ny;
@@ -1952,6 +1964,7 @@ int batch_upload(hj_batch b, int inst, int field, const void* src, bool src_f64)
     if (int rc = check_batch(b)) return rc;
     if (inst < 0 || inst >= b->n) return set_err(HJ_ERR_ARG, "instance %d out of range", inst);
     if (!src) return set_err(HJ_ERR_ARG, "host_src is NULL");
+    if (host_mem(src) == HostMem::device) return set_err(HJ_ERR_ARG, "host_src is device memory, not a host array");
     if (field == HJ_WRK2) return set_err(HJ_ERR_ARG, "HJ_WRK2 cannot be uploaded");
     if (field < 0 || field >= HJ_WRK2) return set_err(HJ_ERR_ARG, "field %d out of range", field);
     return guarded([&]() -> int {
@@ -1987,6 +2000,7 @@ int hj_batch_download(hj_batch b, int inst, int field, void* dst)
     if (int rc = check_batch(b)) return rc;
     if (inst < 0 || inst >= b->n) return set_err(HJ_ERR_ARG, "instance %d out of range", inst);
     if (!dst) return set_err(HJ_ERR_ARG, "host_dst is NULL");
+    if (host_mem(dst) == HostMem::device) return set_err(HJ_ERR_ARG, "host_dst is device memory, not a host array");
     if (field < 0 || field >= HJ_NFIELDS) return set_err(HJ_ERR_ARG, "field %d out of range", field);
     return guarded([&]() -> int {
         int q = field;

@@ -239,6 +239,24 @@ def test_error_paths():
     assert lib.hj_sweep(h, 1, 0.8, None, None) == -7     # destroyed handle
 
 
+def test_device_memory_is_not_a_host_array():
+    """A device pointer passed where the ABI takes a host array is refused
+    with HJ_ERR_ARG, not copied through the host."""
+    import torch
+    shape = (5, 6, 7)
+    dev = torch.zeros(int(np.prod(shape)), dtype=torch.float64, device="cuda")
+    lib = hj.load()
+    with hj.Solver("f64", shape) as s:
+        assert lib.hj_upload(s._h, 1, dev.data_ptr()) == -1
+        assert lib.hj_upload_f64(s._h, 1, dev.data_ptr()) == -1
+        assert lib.hj_download(s._h, 0, dev.data_ptr()) == -1
+        assert lib.hj_snapshot(s._h, dev.data_ptr()) == -1
+        assert b"device memory" in lib.hj_last_error()
+    with hj.Batch("f64", [shape, (4, 4, 4)]) as b:
+        assert lib.hj_batch_upload(b._h, 0, 1, dev.data_ptr()) == -1
+        assert lib.hj_batch_download(b._h, 0, 0, dev.data_ptr()) == -1
+
+
 def test_out_of_memory_is_reported_and_recoverable():
     """A grid larger than the device (about 3 TB of arrays) fails with
     HJ_ERR_OOM, and later handles work normally (the error is not kept)."""
