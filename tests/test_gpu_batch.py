@@ -216,3 +216,35 @@ def test_batch_genetic_search_keeps_parity():
         for t, a in enumerate(arrays):
             pref, _, _ = oracle.sweep(a, 4, 0.8)
             assert np.array_equal(b.download(t), pref)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_pinned_host_arrays_match_pageable(dtype):
+    """Batch uploads from and downloads into pinned host memory (copied
+    directly) give the same instances as pageable arrays."""
+    from paper_2002_12115_amd import transfer
+    shapes, seeds = inputs.batch_shapes(21, 4, lo_xy=4, hi_xy=30, lo_z=4, hi_z=90)
+    arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
+    say("batch pinned", dtype)
+    outs = {}
+    for pinned in (False, True):
+        with hj.Batch(dtype, shapes) as b:
+            for t, a in enumerate(arrays):
+                src = {n: transfer.pinned_like(a[n], b.np_dtype) for n in inputs.INPUTS} if pinned else a
+                b.upload_all(t, src)
+            b.sweep(4, 0.8)
+            got = []
+            for t, sh in enumerate(shapes):
+                if pinned:
+                    out = transfer.pinned_like(np.zeros(sh), b.np_dtype)
+                    lib = hj.load()
+                    assert lib.hj_batch_download(b._h, t, 0, out.ctypes.data) == 0
+                    got.append(out.copy())
+                else:
+                    got.append(b.download(t))
+            outs[pinned] = got
+    for x, y in zip(outs[False], outs[True]):
+        assert np.array_equal(x, y)
+    if dtype == "f64":
+        for t, a in enumerate(arrays):
+            assert np.array_equal(outs[True][t], oracle.sweep(a, 4, 0.8)[0])

@@ -442,6 +442,23 @@ def test_snapshots_equal_the_field_when_taken():
         assert res[policy]["d2h_bytes"] == 4 * f["p"].size * 8
 
 
+def test_f32_snapshot_equals_download():
+    from paper_2002_12115_amd import transfer
+    shape = (17, 40, 130)
+    f = inputs.fields(12, shape)
+    say("f32 snapshot")
+    with hj.Solver("f32", shape) as s:
+        s.upload_all(f)
+        s.sweep(3, 0.8)
+        snap = transfer.pinned_like(np.zeros(shape), np.float32)
+        s.snapshot(snap)
+        want = s.download()
+        s.sweep(3, 0.8)
+        s.snapshot_wait()
+        assert np.array_equal(snap, want)
+        assert field_err(snap, oracle.sweep(f, 3, 0.8)[0]) <= F32_FIELD_RTOL
+
+
 def test_flat_fit_is_enforced():
     """A flat run too wide for the grid is refused, never launched."""
     # FP64 staged plane: 1280 values. nz = 300: runs of 128 cells touch 4 rows
