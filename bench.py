@@ -7,7 +7,9 @@ host (hj_sweep). Inputs are uploaded before the timed region. The printed
 JSON line reports GLUPS (interior lattice updates per second) over the
 timed steps, the dominant kernel's algorithmic HBM bandwidth against the
 8 TB/s peak, the field and gosa error against the FP64 CPU oracle, and the
-oracle itself timed on the host cores as a reported baseline.
+oracle itself timed on the host cores as a reported baseline. The oracle runs
+only in that last leg (cpu_baseline_leg): the GPU legs keep the results to
+check, and the leg times the oracle and compares them with it.
 
   python bench.py [--steps K] [--warmup W] [--workload medium_f64] [--tune]
                   [--no-cpu-baseline] [--no-extra] [--profile]
@@ -225,18 +227,15 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
         log("configuration from the tuning cache:", s.config)
     cfg = s.config.as_dict()
 
-    # accuracy of the first solve from the initial field
-    acc = None
+    # the first solve's result from the initial field, kept for the
+    # cpu_baseline leg to compare with the oracle
+    check = None
     if check_iters:
         # whole grids: the first check_iters iterations; sampled cells: one
         # pass of the configured kernel
         n_chk = min(check_iters, w.iters) if arrays is not None else max(2, int(cfg.get("tsteps", 1)))
         s.sweep(n_chk, w.omega)
-        if arrays is not None:
-            acc = accuracy(w, arrays, s.download("p"), s.gosa_history.copy(), n_chk)
-        else:
-            acc = sampled_accuracy(w, inputs, s.download("p"), n_chk)
-        log("accuracy", acc)
+        check = {"w": w, "n": n_chk, "p": s.download("p"), "hist": s.gosa_history.copy(), "arrays": arrays}
         if arrays is not None:
             s.upload("p", arrays["p"])
         else:
@@ -285,7 +284,7 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
         "hbm_gbps_alg": achieved, "frac_peak": achieved / PEAK_HBM_GBPS,
         "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_launch, "launches": launches,
         "upload_s": upload_s, "pcie_inclusive_glups": updates / (wall + upload_s) / 1e9,
-        "traffic": traffic, "config": cfg, "tuned_ms": tuned_ms, "accuracy": acc,
+        "traffic": traffic, "config": cfg, "tuned_ms": tuned_ms, "accuracy": None, "check": check,
         "last_gosa": float(s.gosa_history[-1]), "steps": steps,
         "step_ms_device": {"median": float(np.median(step_ms)), "min": float(min(step_ms)),
                            "max": float(max(step_ms))},
@@ -407,9 +406,9 @@ def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune
             "hbm_gbps_alg": 14 * esize(dtype) * n_int * iters * args.batch_steps / wall / 1e9}
 
 
-def batch_accuracy(hj, inputs, n_iter: int):
-    """FP32 batched field error against the FP64 oracle, per instance (max)."""
-    import oracle
+def batch_result(hj, inputs, n_iter: int):
+    """The FP32 batch's fields after n_iter iterations, with their inputs, for
+    the cpu_baseline leg to compare with the oracle."""
     w = inputs.WORKLOADS["batch64"]
     shapes, seeds = inputs.batch_shapes(w.seed, w.batch)
     b = hj.Batch("f32", shapes)
@@ -419,13 +418,36 @@ def batch_accuracy(hj, inputs, n_iter: int):
         arrs.append(a)
         b.upload_all(t, a)
     b.sweep(n_iter, w.omega)
-    worst = 0.0
-    for t, a in enumerate(arrs):
-        pref, _, _ = oracle.sweep(a, n_iter, w.omega, nthreads=oracle.max_threads())
-        p = b.download(t).astype(np.float64)
-        worst = max(worst, float(np.abs(p - pref).max() / np.abs(pref).max()))
+    out = [b.download(t) for t in range(len(shapes))]
     b.close()
-    return {"field_rel_err_max": worst, "iters_checked": n_iter}
+    return {"w": w, "n": n_iter, "arrays": arrs, "p": out}
+
+
+def batch_accuracy(r):
+    """FP32 batched field error against the FP64 oracle, per instance (max)."""
+    import oracle
+    worst = 0.0
+    for a, p in zip(r["arrays"], r["p"]):
+        pref, _, _ = oracle.sweep(a, r["n"], r["w"].omega, nthreads=oracle.max_threads())
+        worst = max(worst, float(np.abs(p.astype(np.float64) - pref).max() / np.abs(pref).max()))
+    return {"field_rel_err_max": worst, "iters_checked": r["n"]}
+
+
+def cpu_baseline_leg(w, arrays, budget_s: float, checks: dict, inputs):
+    """The only part of this script that runs the oracle: its timing on the
+    host cores, and the error of every checked GPU result against it.
+    checks: name -> the result a GPU leg kept (see run_single, batch_result)."""
+    acc = {}
+    for name, c in checks.items():
+        if c is None:
+            continue
+        if "hist" in c:
+            acc[name] = (accuracy(c["w"], c["arrays"], c["p"], c["hist"], c["n"]) if c["arrays"] is not None
+                         else sampled_accuracy(c["w"], inputs, c["p"], c["n"]))
+        else:
+            acc[name] = batch_accuracy(c)
+        log("accuracy", name, acc[name])
+    return cpu_baseline(w, arrays, budget_s), acc
 
 
 def main():
@@ -521,9 +543,7 @@ def main():
         "upload_s": res["upload_s"],
         "pcie_inclusive_glups": res["pcie_inclusive_glups"],
     }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)...")
-        out["cpu_baseline"] = cpu_baseline(w, arrays, args.cpu_budget)
+    checks = {"main": res.pop("check")}
     if not args.no_extra:
         extra = {}
         log("tuner comparison...")
@@ -538,17 +558,27 @@ def main():
         extra["batch64_f64_per_instance"] = run_batch(args, hj, inputs, "f64", 100, True, False)
         extra["batch64_f32_vs_f64_per_instance"] = (extra["batch64_f32_batched"]["glups"]
                                                     / extra["batch64_f64_per_instance"]["glups"])
-        log("batch64 FP32 accuracy...")
-        extra["batch64_f32_accuracy"] = batch_accuracy(hj, inputs, 10)
+        checks["batch64_f32"] = batch_result(hj, inputs, 10)
         saved = args.ceilings
         args.ceilings = False
         for name, steps, chk, keep in (("large_f32", 3, 20, True), ("huge_f32", 2, 2, False)):
             log(name, "...")
             r, _ = run_single(inputs.WORKLOADS[name], args, hj, inputs, steps, 1, chk, keep)
+            checks[name] = r.pop("check")
             extra[name] = {k: r[k] for k in ("glups", "ms_per_step", "hbm_gbps_alg", "frac_peak",
-                                             "avg_launch_ms", "config", "accuracy", "steps", "upload_s")}
+                                             "avg_launch_ms", "config", "steps", "upload_s")}
         args.ceilings = saved
         out["extra"] = extra
+    if not args.no_cpu_baseline:
+        log("cpu baseline leg (oracle): timing and the error of every checked result...")
+        out["cpu_baseline"], acc = cpu_baseline_leg(w, arrays, args.cpu_budget, checks, inputs)
+        out["accuracy"] = acc.get("main")
+        if "extra" in out:
+            for name in ("large_f32", "huge_f32"):
+                if name in out["extra"]:
+                    out["extra"][name]["accuracy"] = acc.get(name)
+            if "batch64_f32" in acc:
+                out["extra"]["batch64_f32_accuracy"] = acc["batch64_f32"]
     print(json.dumps(out), flush=True)
 
 
