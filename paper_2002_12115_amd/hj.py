@@ -363,8 +363,14 @@ class Batch:
         for n in INPUTS:
             self.upload(inst, n, arrays[n])
 
-    def download(self, inst: int, name="p") -> np.ndarray:
-        out = np.empty(self.shapes[inst], dtype=self.np_dtype)
+    def download(self, inst: int, name="p", out: Optional[np.ndarray] = None) -> np.ndarray:
+        """Instance inst's field as a new array, or written into `out`
+        (C-contiguous, the instance's shape and the batch's dtype)."""
+        shape = tuple(self.shapes[inst])
+        if out is None:
+            out = np.empty(shape, dtype=self.np_dtype)
+        elif out.shape != shape or out.dtype != self.np_dtype or not out.flags.c_contiguous:
+            raise ValueError("out must be a C-contiguous %s array of shape %s" % (self.np_dtype, shape))
         check(self.lib.hj_batch_download(self._h, inst, _field(name), out.ctypes.data), "hj_batch_download")
         return out
 

@@ -236,12 +236,11 @@ def test_batch_pinned_host_arrays_match_pageable(dtype):
             got = []
             for t, sh in enumerate(shapes):
                 if pinned:
-                    out = transfer.pinned_like(np.zeros(sh), b.np_dtype)
-                    lib = hj.load()
-                    assert lib.hj_batch_download(b._h, t, 0, out.ctypes.data) == 0
-                    got.append(out.copy())
+                    got.append(b.download(t, out=transfer.pinned_like(np.zeros(sh), b.np_dtype)).copy())
                 else:
                     got.append(b.download(t))
+            with pytest.raises(ValueError):
+                b.download(0, out=np.zeros((2, 2, 2), dtype=b.np_dtype))
             outs[pinned] = got
     for x, y in zip(outs[False], outs[True]):
         assert np.array_equal(x, y)
