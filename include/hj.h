@@ -194,7 +194,19 @@ int hj_set_config(hj_solver h, const hj_config* cfg);
  * n_sweeps per timing (>= 1; an even count times two-iteration passes
  * without a one-iteration remainder), repeats (>= 1): the median of the
  * repeats is scored.
- * best (nullable) receives the chosen configuration, best_ms its time. */
+ * best (nullable) receives the chosen configuration, best_ms its time.
+ * HJ_ERR_TUNE when no candidate passed; the configuration then stays as it
+ * was. On any error the field is restored and the previous configuration
+ * kept. The device memory the search uses (a saved copy of the field and the
+ * parity reference) is freed before the call returns.
+ * Environment: HJ_TUNE_LOG=<file> appends one CSV line per measurement
+ * (configuration, median ms, and "ok", "launch-failed" or "parity-failed").
+ * HJ_TUNE_INJECT exercises the failure paths from the host: rules separated
+ * by ';', each "launch:" or "parity:" followed by field=value pairs joined by
+ * ',' (field names of hj_config), e.g. "launch:tsteps=2;parity:kernel=2". A
+ * candidate whose fields match a launch rule scores as a failed launch
+ * without running; one matching a parity rule runs and then scores as a
+ * parity failure. No kernel is altered. */
 int hj_autotune(hj_solver h, int n_sweeps, int repeats, hj_config* best, double* best_ms);
 
 /* The paper's genetic search (sections 4 and 5.1.2) as the search strategy

@@ -83,15 +83,36 @@ def _ptrs(work: Mapping[str, np.ndarray]):
     return (ctypes.c_void_p * 14)(*[work[n].ctypes.data for n in ORDER])
 
 
+def _in_place(arrays: Mapping[str, np.ndarray]) -> Tuple[Dict[str, np.ndarray], Tuple[int, int, int]]:
+    """The caller's own arrays (FP64, C-contiguous, one shape), with a wrk2
+    made from p when none is given: no copy of the 13 inputs."""
+    shape = np.asarray(arrays["p"]).shape
+    work = {}
+    for name in ORDER:
+        if name == "wrk2" and "wrk2" not in arrays:
+            work[name] = np.array(arrays["p"], dtype=np.float64, order="C", copy=True)
+            continue
+        a = arrays[name]
+        if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous or a.shape != shape:
+            raise ValueError("copy=False needs C-contiguous float64 arrays of one shape (%s)" % name)
+        work[name] = a
+    if len(shape) != 3:
+        raise ValueError("arrays must be 3-D [nx][ny][nz]")
+    return work, shape
+
+
 def sweep(arrays: Mapping[str, np.ndarray], n_iter: int, omega: float,
-          nthreads: int = 1) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """n_iter Jacobi iterations from the given arrays (not modified).
+          nthreads: int = 1, copy: bool = True) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """n_iter Jacobi iterations from the given arrays.
 
     Returns (p, wrk2, gosa_hist): the field after the last iteration, the
     last iteration's wrk2 (shell copied from the initial p when wrk2 is not
     given), and the per-iteration gosa, each from the pre-update field.
+    With copy=True (the default) the arrays are copied and left unchanged;
+    with copy=False they must be C-contiguous float64 arrays, and p (and
+    wrk2, when given) are updated in place -- for grids too large to hold twice.
     """
-    work, (nx, ny, nz) = _prepare(arrays)
+    work, (nx, ny, nz) = _prepare(arrays) if copy else _in_place(arrays)
     hist = np.zeros(max(n_iter, 0), dtype=np.float64)
     rc = _load().oracle_sweep(nx, ny, nz, _ptrs(work), int(n_iter), float(omega),
                               hist.ctypes.data if n_iter > 0 else None, int(nthreads))

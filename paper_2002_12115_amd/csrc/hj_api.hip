@@ -247,41 +247,49 @@ bool capture_disturbed(hipError_t e)
 
 // ---- device buffers -----------------------------------------------------------
 
-struct DevBuf {
+// A buffer the library allocates on demand and frees when its owner goes
+// away (or at release()). Move-only: exactly one owner frees it.
+template <void (*Alloc)(void**, size_t), void (*Free)(void*)>
+struct OwnedBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    OwnedBuf() = default;
+    OwnedBuf(const OwnedBuf&) = delete;
+    OwnedBuf& operator=(const OwnedBuf&) = delete;
+    OwnedBuf(OwnedBuf&& o) noexcept : p(o.p), bytes(o.bytes)
+    {
+        o.p = nullptr;
+        o.bytes = 0;
+    }
+    OwnedBuf& operator=(OwnedBuf&& o) noexcept
+    {
+        if (this != &o) {
+            release();
+            p = o.p;
+            bytes = o.bytes;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
+    ~OwnedBuf() { release(); }
     void ensure(size_t need)
     {
         if (need <= bytes) return;
         release();
-        dev_alloc(&p, need);
+        Alloc(&p, need);
         bytes = need;
     }
     void release()
     {
-        if (p) dev_free(p);
+        if (p) Free(p);
         p = nullptr;
         bytes = 0;
     }
 };
 
-struct PinBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    void ensure(size_t need)
-    {
-        if (need <= bytes) return;
-        release();
-        host_alloc(&p, need);
-        bytes = need;
-    }
-    void release()
-    {
-        if (p) host_free(p);
-        p = nullptr;
-        bytes = 0;
-    }
-};
+using DevBuf = OwnedBuf<dev_alloc, dev_free>;   // device memory
+using PinBuf = OwnedBuf<host_alloc, host_free>; // pinned host memory
 
 struct GraphEntry {
     int n_iter;
@@ -308,8 +316,14 @@ int chunk_iters(int n_iter, long long tiles)
     return (int)ch;
 }
 
+// The executable graphs of a handle's recent loops (at most 8, oldest
+// evicted first). Graphs are launched on the handle's stream `st`; before
+// an exec is destroyed, that stream is drained, so no launch of it can
+// still be queued or running. (A stream under capture by the caller has run
+// nothing yet: it is not drained.)
 struct GraphCache {
     std::vector<GraphEntry> v;
+    hipStream_t st = nullptr;
     hipGraphExec_t find(int n, double omega, int parity, const hj_config& c, double* out)
     {
         for (auto& e : v)
@@ -318,9 +332,18 @@ struct GraphCache {
                 return e.exec;
         return nullptr;
     }
+    void drain()
+    {
+        if (!st) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+            (void)hipStreamSynchronize(st);
+        (void)hipGetLastError();
+    }
     void add(const GraphEntry& e)
     {
         if (v.size() >= 8) {
+            drain();
             exec_destroy(v.front().exec);
             v.erase(v.begin());
         }
@@ -328,6 +351,8 @@ struct GraphCache {
     }
     void clear()
     {
+        if (v.empty()) return;
+        drain();
         for (auto& e : v) exec_destroy(e.exec);
         v.clear();
     }
@@ -528,6 +553,59 @@ struct TuneOps {
     std::function<std::vector<std::pair<const void*, size_t>>()> result;
 };
 
+// Host-side failure injection for the tuner's error paths (no kernel is
+// changed and nothing faults): HJ_TUNE_INJECT holds rules separated by ';',
+// each "launch:<field>=<v>,..." or "parity:<field>=<v>,...", with fields named
+// as in hj_config. A candidate matching every field of a launch rule is
+// scored as if it had failed to launch (it is not run); one matching a parity
+// rule is run and then scored as if its field differed from the reference's.
+enum class Inject { none, launch, parity };
+
+Inject injected_failure(const hj_config& c)
+{
+    const char* env = getenv("HJ_TUNE_INJECT");
+    if (!env || !*env) return Inject::none;
+    const std::pair<const char*, int> fields[] = {
+        {"kernel", c.kernel},       {"bj", c.bj},           {"vec", c.vec},
+        {"ichunk", c.ichunk},       {"nontemporal", c.nontemporal}, {"use_graph", c.use_graph},
+        {"xcd_remap", c.xcd_remap}, {"persistent", c.persistent},   {"tsteps", c.tsteps},
+        {"reread", c.reread}};
+    std::string all(env);
+    size_t pos = 0;
+    while (pos <= all.size()) {
+        size_t end = all.find(';', pos);
+        if (end == std::string::npos) end = all.size();
+        const std::string rule = all.substr(pos, end - pos);
+        pos = end + 1;
+        const size_t colon = rule.find(':');
+        if (colon == std::string::npos) continue;
+        const std::string mode = rule.substr(0, colon);
+        if (mode != "launch" && mode != "parity") continue;
+        bool match = true, any = false;
+        size_t q = colon + 1;
+        while (q < rule.size() && match) {
+            size_t e = rule.find(',', q);
+            if (e == std::string::npos) e = rule.size();
+            const std::string kv = rule.substr(q, e - q);
+            q = e + 1;
+            const size_t eq = kv.find('=');
+            if (eq == std::string::npos) { match = false; break; }
+            const std::string name = kv.substr(0, eq);
+            const int val = atoi(kv.c_str() + eq + 1);
+            bool known = false;
+            for (const auto& f : fields)
+                if (name == f.first) {
+                    known = true;
+                    match = match && f.second == val;
+                }
+            match = match && known;
+            any = true;
+        }
+        if (match && any) return mode == "launch" ? Inject::launch : Inject::parity;
+    }
+    return Inject::none;
+}
+
 // Times configurations on the caller's arrays. The first configuration
 // evaluated is the reference; every later one must leave a result bitwise
 // equal to it after the same sweeps, or it scores as failed (INFINITY).
@@ -541,6 +619,11 @@ struct Evaluator {
 
     double eval(const hj_config& c)
     {
+        const Inject inj = injected_failure(c);
+        if (inj == Inject::launch) {
+            tune_log(kind, dtype, nx, ny, nz, c, INFINITY, "launch-failed");
+            return INFINITY;
+        }
         try {
             ops.set(c);
             ops.restore();
@@ -549,6 +632,11 @@ struct Evaluator {
             (void)hipGetLastError();
             tune_log(kind, dtype, nx, ny, nz, c, INFINITY, "launch-failed");
             return INFINITY;  // a candidate that does not launch is never chosen
+        }
+        if (inj == Inject::parity) {
+            HIPCHK(hipStreamSynchronize(ops.st));
+            tune_log(kind, dtype, nx, ny, nz, c, INFINITY, "parity-failed");
+            return INFINITY;
         }
         const std::vector<std::pair<const void*, size_t>> res = ops.result();
         if (!have_ref) {
@@ -855,6 +943,7 @@ int solver_init(hj_solver* out, int dtype, int nx, int ny, int nz, void* dev_sla
         stream_create(&h->cap);
         HIPCHK(hipEventCreate(&h->ev0));
         HIPCHK(hipEventCreate(&h->ev1));
+        h->graphs.st = h->stream;
     } catch (...) {
         if (h->owns_slab && h->slab) dev_free(h->slab);
         if (h->owns_stream && h->stream) stream_destroy(h->stream);
@@ -1402,12 +1491,30 @@ int hj_set_config(hj_solver h, const hj_config* cfg)
 namespace {
 
 // Tuning operations over a single solve: the saved state is the current
-// field, restored into both halves of the ping-pong pair.
+// field, restored into both halves of the ping-pong pair. The saved copy and
+// the evaluator's buffers are freed with the session. If the session ends
+// without finish() (an exception), the field and configuration are put back.
 struct SolverTuning {
     hj_solver h;
     DevBuf save;
     Evaluator ev;
     hj_config keep;
+    bool saved = false, finished = false;
+
+    SolverTuning(const SolverTuning&) = delete;
+    SolverTuning& operator=(const SolverTuning&) = delete;
+    ~SolverTuning()
+    {
+        if (finished) return;
+        try {
+            if (saved) restore();
+            (void)hipStreamSynchronize(h->stream);
+            h->graphs.clear();
+        } catch (...) {
+        }
+        (void)hipGetLastError();
+        h->cfg = keep;
+    }
 
     SolverTuning(hj_solver hh, int n_sweeps, int repeats) : h(hh)
     {
@@ -1416,6 +1523,7 @@ struct SolverTuning {
         save.ensure(L.field_bytes);
         HIPCHK(hipMemcpyAsync(save.p, h->field(h->parity ? HJ_WRK2 : HJ_P), L.field_bytes,
                               hipMemcpyDeviceToDevice, h->stream));
+        saved = true;
         ev.n_sweeps = n_sweeps;
         ev.repeats = repeats;
         ev.kind = "solve";
@@ -1451,6 +1559,7 @@ struct SolverTuning {
         restore();
         HIPCHK(hipStreamSynchronize(h->stream));
         h->graphs.clear();
+        finished = true;
         if (!std::isfinite(win_ms)) {
             h->cfg = keep;
             return set_err(HJ_ERR_TUNE, "no candidate configuration passed");
@@ -1940,6 +2049,7 @@ int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* n
             int dev = 0;
             HIPCHK(hipGetDevice(&dev));
             HIPCHK(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev));
+            b->graphs.st = b->stream;
         } catch (...) {
             if (b->slab) dev_free(b->slab);
             if (b->owns_stream && b->stream) stream_destroy(b->stream);
@@ -2081,13 +2191,32 @@ int hj_batch_set_config(hj_batch b, const hj_config* cfg)
 
 namespace {
 
-// Tuning operations over a batch: the saved state is the whole slab.
+// Tuning operations over a batch: the saved state is the whole slab (a
+// second slab's worth of device memory, held for the session only). As for
+// a single solve, an exception puts the slab and configuration back.
 struct BatchTuning {
     hj_batch b;
     DevBuf save;
     Evaluator ev;
     hj_config keep;
     int par0;
+    bool saved = false, finished = false;
+
+    BatchTuning(const BatchTuning&) = delete;
+    BatchTuning& operator=(const BatchTuning&) = delete;
+    ~BatchTuning()
+    {
+        if (finished) return;
+        try {
+            if (saved) restore();
+            (void)hipStreamSynchronize(b->stream);
+            b->graphs.clear();
+        } catch (...) {
+        }
+        (void)hipGetLastError();
+        b->cfg = keep;
+        b->tiled = false;
+    }
 
     BatchTuning(hj_batch bb, int n_sweeps, int repeats) : b(bb)
     {
@@ -2095,6 +2224,7 @@ struct BatchTuning {
         par0 = b->parity;
         save.ensure(b->slab_bytes);
         HIPCHK(hipMemcpyAsync(save.p, b->slab, b->slab_bytes, hipMemcpyDeviceToDevice, b->stream));
+        saved = true;
         ev.n_sweeps = n_sweeps;
         ev.repeats = repeats;
         ev.kind = "batch";
@@ -2130,6 +2260,7 @@ struct BatchTuning {
         restore();
         HIPCHK(hipStreamSynchronize(b->stream));
         b->graphs.clear();
+        finished = true;
         if (!std::isfinite(win_ms)) {
             b->cfg = keep;
             b->tiled = false;
