@@ -5,13 +5,15 @@ A step is one full solve of the workload on resident arrays: n_iter Jacobi
 iterations with the fused FP64 gosa of every iteration brought back to the
 host (hj_sweep). Inputs are uploaded before the timed region. The printed
 JSON line reports GLUPS (interior lattice updates per second) over the
-timed steps, the dominant kernel's algorithmic HBM bandwidth against the
-8 TB/s peak, the field and gosa error against the FP64 CPU oracle, and the
-oracle itself timed on the host cores as a reported baseline. The oracle runs
-only in that last leg (cpu_baseline_leg): the GPU legs keep the results to
-check, and the leg times the oracle and compares them with it.
+timed steps; the dominant kernel's HBM rate against the 8 TB/s peak, both
+algorithmic (the bytes a pass must move: each of the 14 arrays once) and
+measured (rocprofv3 counter bytes, when taken on the current kernel code);
+the field and gosa error of every result against the FP64 CPU oracle; and
+the oracle itself timed on the host cores as a reported baseline. The oracle
+runs only in that last leg (cpu_baseline_leg): the GPU legs keep the results
+to check, and the leg times the oracle and compares them with it.
 
-  python bench.py [--steps K] [--warmup W] [--workload medium_f64] [--tune]
+  python bench.py [--steps K] [--warmup W] [--workload medium_f64] [--retune]
                   [--no-cpu-baseline] [--no-extra] [--profile]
 """
 from __future__ import annotations
@@ -121,6 +123,38 @@ def load_traffic(workload: str, cfg: dict):
     return e.get("bytes_per_launch")
 
 
+def roofline(esz: int, n_int: int, tsteps: int, avg_launch_ms: float, traffic):
+    """HBM figures of one launch of a kernel that advances every interior cell
+    of n_int by tsteps iterations in one pass over memory.
+
+    achieved: algorithmic bytes per launch / average launch time. The
+    algorithmic bytes are what the pass must move at least: the 12
+    coefficient arrays and p read once and wrk2 written once per interior
+    cell, 14 * esz * n_int, i.e. 14 * esz / tsteps per lattice update (112 B
+    FP64, 56 B FP32 with one iteration per pass; half with two). It is a lower
+    bound on the real traffic, so frac never exceeds what HBM moved.
+    measured: rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch (calibrated
+    against a copy of known size) / the same time, when the counters were
+    taken on the current kernel code and configuration (else null).
+    per_update_equiv: the bytes a one-iteration kernel would move for the
+    same updates, per second (a speed figure, not a fraction of HBM)."""
+    s = avg_launch_ms * 1e-3
+    alg = 14 * esz * n_int
+    out = {"bound": "hbm", "achieved": alg / s / 1e9, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+           "frac": alg / s / 1e9 / PEAK_HBM_GBPS, "traffic": traffic,
+           "achieved_basis": "algorithmic: 14 arrays x %d B x %d interior cells per launch (%d iteration%s)"
+                             % (esz, n_int, tsteps, "s" if tsteps > 1 else ""),
+           "iterations_per_launch": tsteps, "lattice_updates_per_launch": n_int * tsteps,
+           "algorithmic_bytes_per_launch": alg, "avg_launch_ms": avg_launch_ms,
+           "measured_gbps": None, "measured_frac": None, "traffic_over_algorithmic": None,
+           "per_update_equiv_gbps": alg * tsteps / s / 1e9}
+    if traffic:
+        out["measured_gbps"] = traffic / s / 1e9
+        out["measured_frac"] = traffic / s / 1e9 / PEAK_HBM_GBPS
+        out["traffic_over_algorithmic"] = traffic / alg
+    return out
+
+
 def cpu_baseline(w, arrays, budget_s: float):
     """Oracle on the host cores: whole grid, as many iterations as fit the
     budget; when the whole solve fits, repeated solves until the budget is
@@ -168,19 +202,16 @@ def accuracy(w, arrays, p_gpu, hist_gpu, iters: int):
             "field_bitwise": bool(np.array_equal(p_gpu.astype(np.float64), pref))}
 
 
-def sampled_accuracy(w, inputs, pn, n: int, m: int = 2000):
-    """Field error after n sweeps on sampled cells, each recomputed by the
-    oracle on its own (2n+1)^3 neighbourhood (grids too large to sweep on the host)."""
+def whole_grid_accuracy(w, inputs, p_gpu, hist_gpu, iters: int):
+    """Field and gosa error of a grid too large to hold twice: the FP64
+    inputs are regenerated and the oracle updates them in place."""
     import oracle
-    rng = np.random.default_rng(11)
-    cells = np.stack([rng.integers(n, s - n, m) for s in w.shape], 1)
-    nb = inputs.neighbourhood(w.seed, w.shape, cells,
-                              dtype=np.float64 if w.dtype == "f64" else np.float32, radius=n)
-    ref = np.array([oracle.sweep({f: nb[f][q] for f in inputs.INPUTS}, n, w.omega)[0][n, n, n]
-                    for q in range(m)])
-    got = pn[cells[:, 0], cells[:, 1], cells[:, 2]].astype(np.float64)
-    return {"field_rel_err": float(np.abs(got - ref).max() / np.abs(ref).max()),
-            "iters_checked": n, "cells_checked": m}
+    f = inputs.fields(w.seed, w.shape)
+    pref, _, href = oracle.sweep(f, iters, w.omega, nthreads=oracle.max_threads(), copy=False)
+    ferr = float(np.abs(p_gpu.astype(np.float64) - pref).max() / np.abs(pref).max())
+    gerr = float(np.max(np.abs(hist_gpu - href) / href))
+    del f, pref
+    return {"field_rel_err": ferr, "gosa_rel_err": gerr, "iters_checked": iters, "cells_checked": "all"}
 
 
 def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, keep_arrays: bool):
@@ -231,9 +262,9 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
     # cpu_baseline leg to compare with the oracle
     check = None
     if check_iters:
-        # whole grids: the first check_iters iterations; sampled cells: one
-        # pass of the configured kernel
-        n_chk = min(check_iters, w.iters) if arrays is not None else max(2, int(cfg.get("tsteps", 1)))
+        # the first check_iters iterations from the initial field, compared
+        # whole with the oracle in the cpu_baseline leg
+        n_chk = min(check_iters, w.iters)
         s.sweep(n_chk, w.omega)
         check = {"w": w, "n": n_chk, "p": s.download("p"), "hist": s.gosa_history.copy(), "arrays": arrays}
         if arrays is not None:
@@ -257,16 +288,15 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
     kernel_ms = sum(step_ms)
     updates = n_int * w.iters * steps
     glups = updates / wall / 1e9
-    # Algorithmic bytes: 13 reads + 1 write per lattice update (14 x element
-    # size). A launch of t iterations updates every interior cell t times; a
+    # A launch of t iterations advances every interior cell t times; a
     # remainder of a solve runs single-iteration launches, whose time is
     # folded in pro rata (one iteration = 1/t of a launch).
     tsteps = max(1, int(cfg.get("tsteps", 1)))
     launches = w.iters * steps / tsteps
-    bytes_per_launch = 14 * esize(w.dtype) * n_int * tsteps
     avg_launch_ms = kernel_ms / launches
-    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     traffic = load_traffic(w.name, cfg)
+    roof = roofline(esize(w.dtype), n_int, tsteps, avg_launch_ms, traffic)
+    roof["kernel"] = kernel_name(cfg)
     ceilings = None
     if args.ceilings:
         # the library's probes on this GPU: a plain copy, and 13 reads + 1 write
@@ -278,13 +308,14 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
         st_ms = min(s.stream_probe(sv, ich, 10) for ich in (2, 4, 8))
         ceilings = {"copy_gbps": 2 * nb / copy_ms / 1e6,
                     "stream13r1w_gbps": 14 * esize(w.dtype) * n_int / st_ms / 1e6}
-        ceilings["frac_of_stream13r1w"] = achieved / ceilings["stream13r1w_gbps"]
+        ceilings["achieved_over_stream13r1w"] = roof["achieved"] / ceilings["stream13r1w_gbps"]
+        if roof["measured_gbps"]:
+            ceilings["measured_over_stream13r1w"] = roof["measured_gbps"] / ceilings["stream13r1w_gbps"]
+    roof["measured_ceilings"] = ceilings
     res = {
-        "glups": glups, "ms_per_step": wall * 1e3 / steps, "wall_s": wall, "ceilings": ceilings,
-        "hbm_gbps_alg": achieved, "frac_peak": achieved / PEAK_HBM_GBPS,
-        "avg_launch_ms": avg_launch_ms, "bytes_per_launch": bytes_per_launch, "launches": launches,
+        "glups": glups, "ms_per_step": wall * 1e3 / steps, "wall_s": wall, "roofline": roof,
         "upload_s": upload_s, "pcie_inclusive_glups": updates / (wall + upload_s) / 1e9,
-        "traffic": traffic, "config": cfg, "tuned_ms": tuned_ms, "accuracy": None, "check": check,
+        "config": cfg, "tuned_ms": tuned_ms, "accuracy": None, "check": check,
         "last_gosa": float(s.gosa_history[-1]), "steps": steps,
         "step_ms_device": {"median": float(np.median(step_ms)), "min": float(min(step_ms)),
                            "max": float(max(step_ms))},
@@ -293,25 +324,49 @@ def run_single(w, args, hj, inputs, steps: int, warmup: int, check_iters: int, k
     return res, arrays
 
 
-def tuner_comparison(w, hj, inputs, arrays):
+def solve_ms(s, w, reps: int = 5) -> float:
+    """Median device time of `reps` whole solves (w.iters iterations) in the
+    handle's installed configuration."""
+    s.sweep(w.iters, w.omega)
+    t = []
+    for _ in range(reps):
+        s.sweep(w.iters, w.omega)
+        t.append(s.last_ms)
+    return float(np.median(t))
+
+
+def tuner_comparison(w, hj, inputs, arrays, sweeps: int = 40, seeds=(2002, 1, 7)):
     """Exhaustive search against the paper's genetic search (population and
-    generations = gene length 10, Pc 0.9, Pm 0.05) on the same arrays."""
-    out = {}
-    for kind in ("exhaustive", "genetic"):
-        s = hj.Solver(w.dtype, w.shape)
-        s.upload_all(arrays)
-        os.environ["HJ_TUNE_CACHE"], saved = "", os.environ.get("HJ_TUNE_CACHE", "")
-        t0 = time.perf_counter()
-        if kind == "exhaustive":
-            c, ms = s.autotune(n_sweeps=6, repeats=3)
-            ev = None
-        else:
-            c, ms, ev = s.autotune_ga(10, 10, w.seed, 0.9, 0.05, n_sweeps=6, repeats=3)
-        dt = time.perf_counter() - t0
+    generations 10, at most the gene length; Pc 0.9, Pm 0.05) on the same
+    arrays. Every measurement times `sweeps` sweeps (2-3 ms on medium_f64, so
+    that timing noise does not decide fitness), median of 3. Each search's
+    winner is then timed on whole solves, and the genetic winner is reported
+    as a fraction of the exhaustive winner's speed, for each seed."""
+    out = {"sweeps_per_measurement": sweeps, "repeats": 3}
+    saved = os.environ.get("HJ_TUNE_CACHE", "")
+    os.environ["HJ_TUNE_CACHE"] = ""              # never write the committed cache
+    try:
+        runs = [("exhaustive", None)] + [("genetic_seed%d" % sd, sd) for sd in seeds]
+        for kind, seed in runs:
+            s = hj.Solver(w.dtype, w.shape)
+            s.upload_all(arrays)
+            t0 = time.perf_counter()
+            if seed is None:
+                c, ms = s.autotune(n_sweeps=sweeps, repeats=3)
+                ev = None
+            else:
+                c, ms, ev = s.autotune_ga(10, 10, seed, 0.9, 0.05, n_sweeps=sweeps, repeats=3)
+            dt = time.perf_counter() - t0
+            solve = solve_ms(s, w)
+            out[kind] = {"config": c.as_dict(), "evaluations": ev, "tune_s": dt,
+                         "search_ms_per_sweep": ms / sweeps, "solve_ms": solve,
+                         "glups": interior(w.shape) * w.iters / solve / 1e6}
+            s.close()
+            log("tuner", kind, c, "%.3f ms per solve" % solve)
+    finally:
         os.environ["HJ_TUNE_CACHE"] = saved
-        out[kind] = {"ms_per_sweep": ms / 6, "config": c.as_dict(), "evaluations": ev, "tune_s": dt,
-                     "hbm_gbps_alg": 14 * esize(w.dtype) * interior(w.shape) / (ms / 6) / 1e6}
-        s.close()
+    ex = out["exhaustive"]["solve_ms"]
+    out["genetic_speed_over_exhaustive"] = {str(sd): ex / out["genetic_seed%d" % sd]["solve_ms"] for sd in seeds}
     return out
 
 
@@ -353,19 +408,33 @@ def one_iteration_config(hj, dtype: str, shape) -> dict:
                 persistent=0, tsteps=1, reread=0)
 
 
-def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune: bool):
+BATCH_MODES = ("batched", "per_instance", "per_instance_default")
+
+
+def run_batch(args, hj, inputs, dtype: str, iters: int, mode: str, tune: bool):
+    """The 64 uneven solves of batch64, `iters` iterations each.
+
+    batched: one launch per pass over every instance's tiles, the loop
+    replayed as one graph (the library's batch path), in its tuned
+    configuration; timed with HIP events around each batch solve.
+    per_instance: one launch per instance per iteration, instance after
+    instance on one stream (the one-iteration kernel, no graph).
+    per_instance_default: each instance its own solve in the library's
+    default configuration (two iterations per launch, graph per solve),
+    still one launch per instance per pass. Both per-instance modes are
+    timed on the host clock around all instances' solves."""
     w = inputs.WORKLOADS["batch64"]
     shapes, seeds = inputs.batch_shapes(w.seed, w.batch)
     n_int = sum(interior(sh) for sh in shapes)
     import torch
-    if per_instance:
-        # one launch per instance per iteration, instance after instance, FP64
+    if mode != "batched":
         solvers = []
         stream = None
         for sh, sd in zip(shapes, seeds):
             s = hj.Solver(dtype, sh, stream=stream)   # all instances on one stream
             stream = stream or s.stream
-            s.config = hj.Config.make(**one_iteration_config(hj, dtype, sh))
+            if mode == "per_instance":
+                s.config = hj.Config.make(**one_iteration_config(hj, dtype, sh))
             s.upload_all(inputs.fields(sd, sh))
             solvers.append(s)
         for s in solvers:
@@ -380,9 +449,14 @@ def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune
             for s in solvers:
                 s.sync()
         wall = time.perf_counter() - t0
-        cfg = dict(one_iteration_config(hj, dtype, shapes[0]), ichunk="about 4096 workgroups per instance")
+        if mode == "per_instance":
+            cfg = dict(one_iteration_config(hj, dtype, shapes[0]), ichunk="about 4096 workgroups per instance")
+        else:
+            cfg = dict(solvers[0].config.as_dict(), ichunk="one wave of resident workgroups per instance")
+        tsteps = 1 if mode == "per_instance" else max(1, int(solvers[0].config.tsteps))
         for s in reversed(solvers):          # the first one owns the shared stream
             s.close()
+        dev_ms = wall * 1e3 / args.batch_steps
     else:
         b = hj.Batch(dtype, shapes)
         for t, (sh, sd) in enumerate(zip(shapes, seeds)):
@@ -395,55 +469,75 @@ def run_batch(args, hj, inputs, dtype: str, iters: int, per_instance: bool, tune
         b.sweep(2, w.omega)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        dms = []
         for _ in range(args.batch_steps):
             b.sweep(iters, w.omega)
+            dms.append(b.last_ms)
         wall = time.perf_counter() - t0
         cfg = b.config.as_dict()
+        tsteps = max(1, int(cfg.get("tsteps", 1)))
         b.close()
+        dev_ms = float(np.median(dms))
+    name = "batch64_%s%s" % (dtype, "" if mode == "batched" else "_" + mode)
+    # one "launch" here is one pass over every instance (a single launch when
+    # batched; one launch per instance otherwise)
+    roof = roofline(esize(dtype), n_int, tsteps, dev_ms / (iters / tsteps), load_traffic(name, cfg))
     return {"glups": n_int * iters * args.batch_steps / wall / 1e9, "dtype": dtype, "iters": iters,
-            "instances": len(shapes), "interior_cells": n_int,
-            "launches_per_iter": len(shapes) if per_instance else 1, "config": cfg,
-            "hbm_gbps_alg": 14 * esize(dtype) * n_int * iters * args.batch_steps / wall / 1e9}
+            "mode": mode, "instances": len(shapes), "interior_cells": n_int,
+            "launches_per_pass": len(shapes) if mode != "batched" else 1, "config": cfg,
+            "ms_per_solve": dev_ms, "roofline": roof}
 
 
-def batch_result(hj, inputs, n_iter: int):
-    """The FP32 batch's fields after n_iter iterations, with their inputs, for
-    the cpu_baseline leg to compare with the oracle."""
+def batch_results(hj, inputs, n_iter: int):
+    """Both dtypes' batched fields and gosa histories after n_iter
+    iterations from the same inputs, for the cpu_baseline leg to compare
+    with the oracle."""
     w = inputs.WORKLOADS["batch64"]
     shapes, seeds = inputs.batch_shapes(w.seed, w.batch)
-    b = hj.Batch("f32", shapes)
-    arrs = []
-    for t, (sh, sd) in enumerate(zip(shapes, seeds)):
-        a = inputs.fields(sd, sh)
-        arrs.append(a)
-        b.upload_all(t, a)
-    b.sweep(n_iter, w.omega)
-    out = [b.download(t) for t in range(len(shapes))]
-    b.close()
-    return {"w": w, "n": n_iter, "arrays": arrs, "p": out}
+    arrs = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
+    out = {"w": w, "n": n_iter, "arrays": arrs}
+    for dtype in ("f64", "f32"):
+        b = hj.Batch(dtype, shapes)
+        for t, a in enumerate(arrs):
+            b.upload_all(t, a)
+        b.sweep(n_iter, w.omega)
+        out[dtype] = {"p": [b.download(t) for t in range(len(shapes))], "hist": b.gosa_history.copy(),
+                      "config": b.config.as_dict()}
+        b.close()
+    return out
 
 
 def batch_accuracy(r):
-    """FP32 batched field error against the FP64 oracle, per instance (max)."""
+    """Per-instance error of both batched dtypes against the FP64 oracle
+    (one oracle solve per instance): FP64 field bitwise and gosa, FP32 field
+    and gosa, the worst instance of each."""
     import oracle
-    worst = 0.0
-    for a, p in zip(r["arrays"], r["p"]):
-        pref, _, _ = oracle.sweep(a, r["n"], r["w"].omega, nthreads=oracle.max_threads())
-        worst = max(worst, float(np.abs(p.astype(np.float64) - pref).max() / np.abs(pref).max()))
-    return {"field_rel_err_max": worst, "iters_checked": r["n"]}
+    acc = {"iters_checked": r["n"], "instances": len(r["arrays"]), "f64_field_bitwise": True,
+           "f64_field_rel_err_max": 0.0, "f64_gosa_rel_err_max": 0.0,
+           "f32_field_rel_err_max": 0.0, "f32_gosa_rel_err_max": 0.0}
+    for t, a in enumerate(r["arrays"]):
+        pref, _, href = oracle.sweep(a, r["n"], r["w"].omega, nthreads=oracle.max_threads())
+        for dt in ("f64", "f32"):
+            p = r[dt]["p"][t].astype(np.float64)
+            fe = float(np.abs(p - pref).max() / np.abs(pref).max())
+            ge = float(np.max(np.abs(r[dt]["hist"][:, t] - href) / href))
+            acc[dt + "_field_rel_err_max"] = max(acc[dt + "_field_rel_err_max"], fe)
+            acc[dt + "_gosa_rel_err_max"] = max(acc[dt + "_gosa_rel_err_max"], ge)
+        acc["f64_field_bitwise"] = acc["f64_field_bitwise"] and bool(np.array_equal(r["f64"]["p"][t], pref))
+    return acc
 
 
 def cpu_baseline_leg(w, arrays, budget_s: float, checks: dict, inputs):
-    """The only part of this script that runs the oracle: its timing on the
-    host cores, and the error of every checked GPU result against it.
-    checks: name -> the result a GPU leg kept (see run_single, batch_result)."""
+    """The only part of this script that runs the oracle: the error of every
+    checked GPU result against it, then its timing on the host cores.
+    checks: name -> the result a GPU leg kept (see run_single, batch_results)."""
     acc = {}
     for name, c in checks.items():
         if c is None:
             continue
         if "hist" in c:
             acc[name] = (accuracy(c["w"], c["arrays"], c["p"], c["hist"], c["n"]) if c["arrays"] is not None
-                         else sampled_accuracy(c["w"], inputs, c["p"], c["n"]))
+                         else whole_grid_accuracy(c["w"], inputs, c["p"], c["hist"], c["n"]))
         else:
             acc[name] = batch_accuracy(c)
         log("accuracy", name, acc[name])
@@ -472,6 +566,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--batch-dtype", default="f32", choices=["f32", "f64"],
                     help="dtype of the batch64 workload when it runs alone (--profile --workload batch64)")
+    ap.add_argument("--batch-mode", default="batched", choices=list(BATCH_MODES),
+                    help="how the batch64 workload runs when it runs alone (--profile --workload batch64)")
     ap.add_argument("--config", default="",
                     help="run the main workload in this configuration instead of the tuned one, "
                          "as field=value pairs, e.g. tsteps=1,vec=2,bj=4,ichunk=2,nontemporal=1")
@@ -497,11 +593,11 @@ def main():
         if not args.profile:
             raise SystemExit("the main line is a single solve; batch64 is reported under extra "
                              "(or run it alone with --profile)")
-        r = run_batch(args, hj, inputs, args.batch_dtype, w.iters, False, args.retune)
+        r = run_batch(args, hj, inputs, args.batch_dtype, w.iters, args.batch_mode, args.retune)
         if args.copy_probe:          # the counters' calibration leg, as for single solves
             ms = hj.copy_probe(args.copy_probe)
             log("copy probe: %d bytes in %.3f ms" % (args.copy_probe, ms))
-        print(json.dumps({"workload": w.name, "batch64_%s_batched" % args.batch_dtype: r}), flush=True)
+        print(json.dumps({"workload": w.name, "batch64_%s_%s" % (args.batch_dtype, args.batch_mode): r}), flush=True)
         return
     if args.profile:
         args.no_cpu_baseline = True
@@ -531,13 +627,7 @@ def main():
                 "wrk1~N(0,0.01), derived a3 and bnd) standing in for the Himeno benchmark",
         "config": {"workload": w.name, "grid": list(w.shape), "iters_per_step": w.iters,
                    "omega": w.omega, "seed": w.seed, "kernel_config": res["config"]},
-        "roofline": {"bound": "hbm", "achieved": res["hbm_gbps_alg"], "peak": PEAK_HBM_GBPS,
-                     "unit": "GB/s", "frac": res["frac_peak"], "traffic": res["traffic"],
-                     "kernel": kernel_name(res["config"]),
-                     "lattice_updates_per_launch": interior(w.shape) * max(1, int(res["config"].get("tsteps", 1))),
-                     "bytes_per_launch": res["bytes_per_launch"],
-                     "avg_launch_ms": res["avg_launch_ms"], "measured_ceilings": res["ceilings"]},
-        "hbm_gbps_alg": res["hbm_gbps_alg"],
+        "roofline": res["roofline"],
         "step_ms_device": res["step_ms_device"],
         "accuracy": res["accuracy"],
         "upload_s": res["upload_s"],
@@ -550,23 +640,23 @@ def main():
         extra["tuner_exhaustive_vs_genetic"] = tuner_comparison(w, hj, inputs, arrays)
         log("transfer placement...")
         extra["transfer_placement"] = transfer_ablation(w, hj, arrays)
-        log("batch64 FP32 batched...")
-        extra["batch64_f32_batched"] = run_batch(args, hj, inputs, "f32", 100, False, args.retune)
-        log("batch64 FP64 batched...")
-        extra["batch64_f64_batched"] = run_batch(args, hj, inputs, "f64", 100, False, args.retune)
-        log("batch64 FP64 one launch per instance...")
-        extra["batch64_f64_per_instance"] = run_batch(args, hj, inputs, "f64", 100, True, False)
-        extra["batch64_f32_vs_f64_per_instance"] = (extra["batch64_f32_batched"]["glups"]
-                                                    / extra["batch64_f64_per_instance"]["glups"])
-        checks["batch64_f32"] = batch_result(hj, inputs, 10)
+        for dtype, mode in (("f32", "batched"), ("f64", "batched"), ("f64", "per_instance"),
+                            ("f64", "per_instance_default")):
+            log("batch64", dtype, mode, "...")
+            extra["batch64_%s_%s" % (dtype, mode)] = run_batch(args, hj, inputs, dtype, 100, mode, args.retune)
+        plain = max(extra["batch64_f64_per_instance"]["glups"], extra["batch64_f64_per_instance_default"]["glups"])
+        extra["batch64_f32_vs_f64_per_instance"] = extra["batch64_f32_batched"]["glups"] / plain
+        log("batch64 results for the oracle...")
+        checks["batch64"] = batch_results(hj, inputs, inputs.WORKLOADS["batch64"].iters)
         saved = args.ceilings
         args.ceilings = False
-        for name, steps, chk, keep in (("large_f32", 3, 20, True), ("huge_f32", 2, 2, False)):
+        # large_f32: the whole 500-iteration solve; huge_f32: 11 iterations
+        # (five two-iteration passes and a one-iteration remainder), whole grid
+        for name, steps, chk, keep in (("large_f32", 3, 500, True), ("huge_f32", 2, 11, False)):
             log(name, "...")
             r, _ = run_single(inputs.WORKLOADS[name], args, hj, inputs, steps, 1, chk, keep)
             checks[name] = r.pop("check")
-            extra[name] = {k: r[k] for k in ("glups", "ms_per_step", "hbm_gbps_alg", "frac_peak",
-                                             "avg_launch_ms", "config", "steps", "upload_s")}
+            extra[name] = {k: r[k] for k in ("glups", "ms_per_step", "roofline", "config", "steps", "upload_s")}
         args.ceilings = saved
         out["extra"] = extra
     if not args.no_cpu_baseline:
@@ -577,8 +667,8 @@ def main():
             for name in ("large_f32", "huge_f32"):
                 if name in out["extra"]:
                     out["extra"][name]["accuracy"] = acc.get(name)
-            if "batch64_f32" in acc:
-                out["extra"]["batch64_f32_accuracy"] = acc["batch64_f32"]
+            if "batch64" in acc:
+                out["extra"]["batch64_accuracy"] = acc["batch64"]
     print(json.dumps(out), flush=True)
 
 
