@@ -168,6 +168,27 @@ int hj_sweep(hj_solver h, int n_iter, double omega, double* gosa_last, double* g
  * gosa goes to dev_gosa_hist (nullable device pointer, n_iter doubles). */
 int hj_sweep_async(hj_solver h, int n_iter, double omega, double* dev_gosa_hist);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * iterations as hj_sweep_async, with the same results bit for bit, but the
+ * call allocates nothing. The per-tile gosa partials go to a file-scope
+ * device array of HJ_NOALLOC_SCRATCH_DOUBLES doubles (4 MiB) instead of the
+ * handle's buffer, and the kernels are enqueued one by one on the handle's
+ * stream (no graph is instantiated). The array's address is looked up when
+ * a handle is created on a device. Only enqueued: dev_gosa_hist (device
+ * pointer, required, n_iter doubles) receives every iteration's gosa.
+ * Errors: HJ_ERR_ARG for a NULL dev_gosa_hist, a current device other than
+ * the one the handle was created on, or a configuration whose per-iteration
+ * partials (one per tile, of the configured kernel or of the one-iteration
+ * kernel that runs remainders) do not fit the array (one iteration's worth,
+ * two for two-iteration passes); HJ_ERR_STATE before every input is
+ * uploaded. Every call on a GPU shares that GPU's array: calls whose work
+ * overlaps on one GPU (other streams, other threads) race and must be
+ * ordered by the caller. Nothing needs clearing between calls (each tile
+ * writes its own slot before it is read). */
+#define HJ_NOALLOC_SCRATCH_DOUBLES 524288
+int hj_sweep_noalloc(hj_solver h, int n_iter, double omega, double* dev_gosa_hist);
+
 /* gosa of the current field, without updating it. Synchronous. */
 int hj_residual(hj_solver h, double* gosa);
 

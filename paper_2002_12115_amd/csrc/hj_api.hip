@@ -759,6 +759,37 @@ bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_c
 
 }  // namespace
 
+// ---- partials of the allocation-free sweep ------------------------------------
+
+// Per-tile gosa partials of hj_sweep_noalloc: a file-scope device array, one
+// copy on every GPU the library runs on, held until the process ends. Host
+// code never passes the array's name to a kernel (in host code it is a
+// stand-in, not a device address): it uses the address hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+static __device__ __align__(256) double scratch[HJ_NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `dev`, which must be the current
+// device; looked up at the first call for that device.
+double* scratch_on(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) throw HipFail{hipErrorInvalidDevice, "scratch_on(dev)", __LINE__};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 // ============================================================================
 // single solve
 // ============================================================================
@@ -766,6 +797,7 @@ bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_c
 struct hj_solver_s {
     uint64_t magic = kSolverMagic;
     int dtype = HJ_F64;
+    int device = 0;           // the device current at creation
     Layout L;
     char* slab = nullptr;
     bool owns_slab = false;
@@ -837,14 +869,17 @@ struct hj_solver_s {
     }
 
     // Enqueue n_iter iterations starting from parity `par`, gosa history to
-    // out. Returns the parity after them (one flip per launch).
-    int enqueue(int n_iter, double omega, int par, double* out, hipStream_t st) const
+    // out. The per-tile partials of up to `ch` iterations (0: chunk_of) at a
+    // time go to pt (null: the handle's buffer), stride() doubles per
+    // iteration. Returns the parity after them (one flip per launch).
+    int enqueue(int n_iter, double omega, int par, double* out, hipStream_t st, double* pt = nullptr,
+                int ch = 0) const
     {
         const bool two = fused_of(cfg);
         const hj_config one = single_cfg();
         const long long sd = stride();
-        const int ch = chunk_of(n_iter);
-        double* pt = static_cast<double*>(part.p);
+        if (ch <= 0) ch = chunk_of(n_iter);
+        if (!pt) pt = static_cast<double*>(part.p);
         for (int it0 = 0; it0 < n_iter;) {
             const int n_here = std::min(ch, n_iter - it0);
             int slot = 0;
@@ -928,6 +963,8 @@ int solver_init(hj_solver* out, int dtype, int nx, int ny, int nz, void* dev_sla
     h->L = L;
     h->cfg = default_config(dtype);
     try {
+        HIPCHK(hipGetDevice(&h->device));
+        (void)scratch_on(h->device);  // set-up of hj_sweep_noalloc on this device
         if (dev_slab) {
             h->slab = static_cast<char*>(dev_slab);
         } else {
@@ -1437,6 +1474,34 @@ int hj_sweep_async(hj_solver h, int n_iter, double omega, double* dev_gosa_hist)
         h->reserve(n_iter);
         double* out = dev_gosa_hist ? dev_gosa_hist : static_cast<double*>(h->gosa.p);
         h->run(n_iter, omega, out);
+        return HJ_OK;
+    });
+}
+
+int hj_sweep_noalloc(hj_solver h, int n_iter, double omega, double* dev_gosa_hist)
+{
+    if (int rc = check_solver(h)) return rc;
+    if (n_iter < 0) return set_err(HJ_ERR_ARG, "n_iter %d < 0", n_iter);
+    if (!dev_gosa_hist) return set_err(HJ_ERR_ARG, "dev_gosa_hist is NULL");
+    const long long sd = h->stride();
+    const bool two = fused_of(h->cfg);
+    const long long fit = (long long)HJ_NOALLOC_SCRATCH_DOUBLES / sd;  // iterations of partials that fit
+    if (fit < (two ? 2 : 1))
+        return set_err(HJ_ERR_ARG, "%lld gosa partials per iteration (%s) exceed the %d-double scratch of "
+                       "hj_sweep_noalloc", sd, two ? "two-iteration passes" : "one-iteration passes",
+                       HJ_NOALLOC_SCRATCH_DOUBLES);
+    if ((h->uploaded & kInputMask) != (unsigned)kInputMask)
+        return set_err(HJ_ERR_STATE, "not every input field is uploaded (mask 0x%x)", h->uploaded);
+    if (n_iter == 0) return HJ_OK;
+    return guarded([&]() -> int {
+        int dev = -1;
+        HIPCHK(hipGetDevice(&dev));
+        if (dev != h->device)
+            return set_err(HJ_ERR_ARG, "current device %d is not the handle's device %d", dev, h->device);
+        int ch = h->chunk_of(n_iter);
+        if (ch > fit) ch = two ? (int)(fit & ~1LL) : (int)fit;
+        // eager launches on the handle's stream: no graph is instantiated
+        h->parity = h->enqueue(n_iter, omega, h->parity, dev_gosa_hist, h->stream, scratch_on(dev), ch);
         return HJ_OK;
     });
 }

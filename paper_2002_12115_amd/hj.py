@@ -84,6 +84,7 @@ def load() -> ctypes.CDLL:
         "hj_snapshot_wait": [H],
         "hj_sweep": [H, i32, dbl, dp, dp],
         "hj_sweep_async": [H, i32, dbl, vp],
+        "hj_sweep_noalloc": [H, i32, dbl, vp],
         "hj_residual": [H, dp],
         "hj_get_config": [H, cp],
         "hj_set_config": [H, cp],
@@ -247,6 +248,12 @@ class Solver:
         check(self.lib.hj_sweep_async(self._h, int(n_iter), float(omega),
                                       ctypes.c_void_p(dev_gosa_hist) if dev_gosa_hist else None),
               "hj_sweep_async")
+
+    def sweep_noalloc(self, n_iter: int, omega: float, dev_gosa_hist: int) -> None:
+        """hj_sweep_noalloc: enqueue n_iter iterations without any allocation;
+        dev_gosa_hist is the device address of n_iter doubles."""
+        check(self.lib.hj_sweep_noalloc(self._h, int(n_iter), float(omega), ctypes.c_void_p(dev_gosa_hist)),
+              "hj_sweep_noalloc")
 
     def residual(self) -> float:
         g = ctypes.c_double()
