@@ -411,6 +411,11 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 template <typename T>
 constexpr int kPrefetchSingle = sizeof(T) == 4 ? 2 : 0;
 
+// Whether a workgroup of `waves` waves (asking for at least min_waves waves
+// per SIMD) leaves each wave the 168 registers of three waves per SIMD, which
+// the prefetching tile's whole-round form needs.
+constexpr bool rounds_ok(int waves, int min_waves) { return waves <= 12 && min_waves <= 3; }
+
 // A thread's first-iteration cell in a two-iteration tile whose p0 tile
 // starts at (j0-2, k0-2): grid cell (j, k), its place (rho, c) in the p0 tile
 // and (r1, c1) in the p1 tile; active: the thread has a cell; own: its cell
@@ -425,11 +430,19 @@ struct TileCell {
 // value that lands outside the grid is never used), so the compiler counts
 // outstanding loads exactly and waits only for the ones a step consumes. The
 // p0 plane i+2+PD and the coefficients of plane i+PD are loaded while plane i
-// is computed, into PD+1 register sets that rotate from step to step, so a
-// load has PD whole steps to arrive. The p0 tile is fetched as a flat array
-// (two cells per thread). Byte offsets within a plane are 32-bit: a plane
-// must hold fewer than 2^32 bytes (plane32_ok).
-template <typename T, typename Lds, bool NT, bool KEEP, int PD>
+// is computed, into PD+2 register sets that rotate from step to step, so a
+// load has PD whole steps to arrive; the set a step computes with serves the
+// next step's second iteration as it is (no copy). The march runs in whole
+// rounds of PD+2 steps, so every set is in the same registers at the loop's
+// back edge (no set is copied there, which would make the copy wait for every
+// load in flight); steps past the chunk's last plane read clamped planes and
+// neither store nor sum anything. This form (ROUNDS) takes more registers;
+// workgroups of more than 12 waves keep the earlier one, PD+1 sets and a copy
+// of the previous plane's coefficients, with the march ending at any step.
+// The p0 tile is fetched as a flat array (two cells per thread). Byte offsets
+// within a plane are 32-bit: a plane must hold fewer than 2^32 bytes
+// (plane32_ok).
+template <typename T, typename Lds, bool NT, bool KEEP, int PD, bool ROUNDS>
 __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0, int k0, const TileCell& tc, int ib,
                                                int ie, Lds& sm, double& acc1, double& acc2)
 {
@@ -478,8 +491,9 @@ __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0
 
     const int i_lo = ib - 1, i_hi = ie;                    // first-iteration planes
     static_assert(PD == 1 || PD == 2, "prefetch distance");
-    constexpr int NS = PD + 1;                             // register sets
+    constexpr int NS = ROUNDS ? PD + 2 : PD + 1;           // register sets
     T ps[NS][2], cs[NS][NCOEF];
+    T kp[ROUNDS ? 1 : NCOEF];                              // the previous plane's set (not ROUNDS)
     for (int ii = i_lo - 1; ii <= i_lo + 1; ++ii) {
         fetch(ii, ps[0]);
         put(ii, ps[0]);
@@ -489,19 +503,30 @@ __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0
         fetch(min(i_lo + 2 + d, i_hi + 1), ps[d]);
         coefs(min(i_lo + d, i_hi), cs[d]);
     }
-    // own cell's coefficients of plane i-1 for the second iteration: kept from
-    // the previous step (KEEP) or loaded again at the start of the step
-    T keep[NCOEF];
+    // the first step's second iteration (plane i_lo-1) has no output: its set
+    // only needs defined values
 #pragma unroll
-    for (int q = 0; q < NCOEF; ++q) keep[q] = T(0);
+    for (int q = 0; q < NCOEF; ++q) {
+        if constexpr (ROUNDS) cs[NS - 1][q] = T(0);
+        else kp[q] = T(0);
+    }
+    // without KEEP the own cell's coefficients of plane i-1 are loaded again
+    // at the start of each step
+    T rk[KEEP ? 1 : NCOEF];
     __syncthreads();
 
     // one step: first iteration at plane i (coefficients cur, p0 planes
-    // i-1 .. i+1 in LDS), second iteration at plane i-1 on the own cells;
+    // i-1 .. i+1 in LDS), second iteration at plane i-1 on the own cells
+    // (coefficients prev: the previous step's cur, or loaded again);
     // loads p0 plane i+2+PD into pf and the coefficients of plane i+PD into
     // nxt, and stores p0 plane i+2 (pp, loaded PD steps earlier) to LDS.
-    auto step = [&](int i, T (&cur)[NCOEF], T (&nxt)[NCOEF], T (&pf)[2], const T (&pp)[2]) {
-        if constexpr (!KEEP) coefs(i - 1, keep);
+    auto step = [&](int i, const T (&cur)[NCOEF], T (&nxt)[NCOEF], const T (&prev)[NCOEF], T (&pf)[2],
+                    const T (&pp)[2]) {
+        const T* keep = prev;
+        if constexpr (!KEEP) {
+            coefs(i - 1, rk);
+            keep = rk;
+        }
         // planes past the chunk's last ones are not needed: load the last
         // ones again (lines the workgroup has just read) instead
         fetch(min(i + 2 + PD, i_hi + 1), pf);
@@ -559,25 +584,38 @@ __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0
             const double d = (double)ss;
             acc2 += d * d;
         }
-        if constexpr (KEEP) {
+        if constexpr (!ROUNDS && KEEP) {
 #pragma unroll
-            for (int q = 0; q < NCOEF; ++q) keep[q] = cur[q];
+            for (int q = 0; q < NCOEF; ++q) kp[q] = cur[q];
         }
     };
 
-    // step number K of each round of NS uses the register sets K, K+PD mod NS
+    // step number K of a round computes with set K, loads into set K+PD and
+    // (ROUNDS) takes the second iteration's coefficients from set K-1 (mod NS)
     auto stepk = [&](auto kc, int i) {
         constexpr int K = decltype(kc)::value;
-        step(i, cs[K % NS], cs[(K + PD) % NS], ps[(K + PD) % NS], ps[K % NS]);
+        if constexpr (ROUNDS)
+            step(i, cs[K % NS], cs[(K + PD) % NS], cs[(K + NS - 1) % NS], ps[(K + PD) % NS], ps[K % NS]);
+        else
+            step(i, cs[K % NS], cs[(K + PD) % NS], kp, ps[(K + PD) % NS], ps[K % NS]);
     };
-    for (int i = i_lo;;) {
-        stepk(std::integral_constant<int, 0>{}, i);
-        if (++i > i_hi) break;
-        stepk(std::integral_constant<int, 1>{}, i);
-        if (++i > i_hi) break;
-        if constexpr (NS > 2) {
-            stepk(std::integral_constant<int, 2>{}, i);
+    if constexpr (ROUNDS) {
+        for (int i = i_lo; i <= i_hi; i += NS) {
+            stepk(std::integral_constant<int, 0>{}, i);
+            stepk(std::integral_constant<int, 1>{}, i + 1);
+            stepk(std::integral_constant<int, 2>{}, i + 2);
+            if constexpr (NS > 3) stepk(std::integral_constant<int, 3>{}, i + 3);
+        }
+    } else {
+        for (int i = i_lo;;) {
+            stepk(std::integral_constant<int, 0>{}, i);
             if (++i > i_hi) break;
+            stepk(std::integral_constant<int, 1>{}, i);
+            if (++i > i_hi) break;
+            if constexpr (NS > 2) {
+                stepk(std::integral_constant<int, 2>{}, i);
+                if (++i > i_hi) break;
+            }
         }
     }
 }
@@ -792,6 +830,14 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
 
 // One workgroup's whole share of a two-iteration pass: tile (kt, jt), i-chunk
 // ic, both iterations' gosa partials to slot L of part1 / part2.
+template <int BJ, int W>
+constexpr int fused_threads() { return (BJ + 2) * W; }
+
+// bj 6 with 64-lane rows asks for four waves per SIMD, so that two of its
+// 8-wave workgroups share a CU (it then holds 128 VGPRs and spills a few).
+template <int BJ, int W>
+constexpr int fused_min_waves() { return (BJ == 6 && W == kWave) ? 4 : 1; }
+
 template <typename T, int BJ, int W, bool NT, bool KEEP, int PF>
 __device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, int jt, int ic, int ichunk, int L,
                                             FusedLds<T, BJ, W>& sm, double* __restrict__ part1,
@@ -805,7 +851,8 @@ __device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, i
         fused_tile<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
     } else {
         const int k0 = 1 + kt * FusedLds<T, BJ, W>::TK, j0 = 1 + jt * BJ;
-        tile2_prefetch<T, FusedLds<T, BJ, W>, NT, KEEP, PF>(g, omega, j0, k0, fused_cell<BJ, W>(j0, k0), ib, ie, sm,
+        tile2_prefetch<T, FusedLds<T, BJ, W>, NT, KEEP, PF, rounds_ok(fused_threads<BJ, W>() / kWave, fused_min_waves<BJ, W>())>(
+            g, omega, j0, k0, fused_cell<BJ, W>(j0, k0), ib, ie, sm,
                                                            acc1, acc2);
     }
     constexpr int NW = FusedLds<T, BJ, W>::NW;
@@ -816,14 +863,6 @@ __device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, i
 }
 
 // Threads per workgroup of the two-iteration kernel with W-lane rows.
-template <int BJ, int W>
-constexpr int fused_threads() { return (BJ + 2) * W; }
-
-// bj 6 with 64-lane rows asks for four waves per SIMD, so that two of its
-// 8-wave workgroups share a CU (it then holds 128 VGPRs and spills a few).
-template <int BJ, int W>
-constexpr int fused_min_waves() { return (BJ == 6 && W == kWave) ? 4 : 1; }
-
 template <typename T, int BJ, int W, bool NT, bool KEEP>
 __global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fused_min_waves<BJ, W>()))) void fused_kernel(
     Grid<T> g, T omega, int ichunk, int kt_n, int jt_n, int remap, double* __restrict__ part1,
@@ -1103,7 +1142,7 @@ __device__ __forceinline__ void wide_block(const Grid<T>& g, T omega, int kt, in
         wide_tile_sync<T, BJ, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
     } else {
         const int k0 = 1 + kt * kWave, j0 = 1 + jt * BJ;
-        tile2_prefetch<T, WideLds<T, BJ>, NT, KEEP, PF>(g, omega, j0, k0, wide_cell<BJ>(j0, k0), ib, ie, sm, acc1,
+        tile2_prefetch<T, WideLds<T, BJ>, NT, KEEP, PF, rounds_ok(BJ + 3, 1)>(g, omega, j0, k0, wide_cell<BJ>(j0, k0), ib, ie, sm, acc1,
                                                        acc2);
     }
     acc1 = block_sum<BJ + 3>(acc1, sm.red);
