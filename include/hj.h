@@ -246,23 +246,27 @@ int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long l
                    double pm, int n_sweeps, int repeats, hj_config* best, double* best_ms,
                    int* evaluations);
 
-/* The configuration a gene names for this problem; every gene names one.
- * bit 0: direct (0) or march (1) kernel; with bit 10 set, flat (0) or march
- * with two iterations per pass (1). bits 1-2: bj 1, 2, 4, 8 (the direct
- * kernel reads 1 as 2; two-iteration passes read the codes as 14, 6, 4, 8).
- * bits 3-4: vec 1, 2, 1, 2 (FP64) or 1, 2, 4, 4 (FP32) for the
- * one-iteration march kernel; for two-iteration passes bit 3 is reread and
- * bit 4 the row layout: vec 2 for single solves (where bj 14 reads as 12),
- * vec 4 for batches (bj codes 14, 6, 22, 30).
- * bits 5-7: the i-chunk n, giving about 512 << n workgroups; for
- * two-iteration passes the longest chunk within 256, 512, 768, 1024, 2048,
- * 4096, 8192 or 24576 workgroups; for batches 2^n planes (one-iteration)
- * or 4 * 2^n planes (two-iteration). bit 8: nontemporal. bit 9: xcd_remap
- * (single solves and two-iteration batches), persistent (one-iteration
- * batches). batch != 0: bit 0 picks flat (0) or march (1), and bit 10 with
- * bit 0 two iterations per pass. A flat kernel that does not fit the grid
- * reads as the march kernel. Returns HJ_ERR_ARG for an unknown dtype.
- * Host only. */
+/* The configuration a gene names for this problem; every gene names one, and
+ * every one of them is among the configurations hj_autotune (or, for batch
+ * != 0, hj_batch_autotune) measures, so both searches cover the same space.
+ * bit 10: two iterations per pass (1) or one (0).
+ * Two iterations (march kernel, nontemporal 0, xcd_remap 1, the settings the
+ * exhaustive search keeps for them): bit 0 the row layout (set: vec 2, 64-cell
+ * rows, for single solves; vec 4, 30-cell rows, for batches; clear: vec 1,
+ * 62-cell rows); bits 1-2 bj (vec 1: 4, 6, 8, 14; vec 2: 4, 6, 8, 12; vec 4:
+ * 6, 14, 22, 30); bit 3 reread; bits 5-7 the i-chunk (single solves: the
+ * longest that keeps the grid within 256, 512, 768, 1024, 1536, 2048, 4096 or
+ * 16384 workgroups; batches: 8, 12, 16, 24, 32, 48, 64 or 128 planes); bits
+ * 4, 8 and 9 unused.
+ * One iteration: bit 0 the march kernel when set; when clear, for single
+ * solves the flat kernel if bit 3 is set, else the direct kernel, and for
+ * batches the flat kernel; bits 1-2 bj 1, 2, 4, 8 (flat and direct read 1 as
+ * 2); bits 3-4 the march kernel's vec 1, 2, 1, 2 (FP64) or 1, 2, 4, 4 (FP32);
+ * bits 5-6 the i-chunk (single solves: the grid of about 1024, 2048, 4096 or
+ * 8192 workgroups; batches: 2, 4, 8 or 16 planes); bit 7 unused; bit 8
+ * nontemporal; bit 9 the march kernel's xcd_remap (single solves) or the
+ * persistent grid (batches). A flat kernel that does not fit the grid reads
+ * as the march kernel. Returns HJ_ERR_ARG for an unknown dtype. Host only. */
 int hj_gene_config(int dtype, int nx, int ny, int nz, int batch, unsigned gene, hj_config* out);
 
 /* The same genetic search with the time of every gene given by a table

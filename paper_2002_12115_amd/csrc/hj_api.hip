@@ -709,50 +709,85 @@ constexpr int kGeneBits = 11;
 // chunks recompute their halo planes and whose workgroups are few and long,
 // the longest chunk within 256, 512, 768, 1024, 2048, 4096, 8192 or 24576
 // workgroups (whole waves on a chip of 256 CUs).
-int gene_ichunk(int sel, const hj_config& c, int nx, int ny, int nz)
-{
-    static const long long kFusedWg[8] = {256, 512, 768, 1024, 2048, 4096, 8192, 24576};
-    if (fused_of(c)) return ichunk_within(c, nx, ny, nz, kFusedWg[sel & 7]);
-    return ichunk_for(c, nx, ny, nz, 512LL << sel);
-}
-
+// The gene (paper sections 4 and 5.1.2: one bit per decision, every value
+// measured) over this kernel's configurations. Every gene names a
+// configuration that the exhaustive search also measures (its candidate list
+// includes every decoded gene), and two-iteration genes carry the settings
+// the exhaustive search keeps for those passes (temporal loads, XCD
+// renumbering), so both searches cover the same space.
+//  bit 10: two iterations per pass (1) or one (0).
+//  two iterations: bit 0 the row layout (set: 64-cell rows with a halo wave
+//    for single solves, two 30-cell rows per wave for batches; clear: 62-cell
+//    rows); bits 1-2 bj (62-cell rows 4, 6, 8, 14; 64-cell rows 4, 6, 8, 12;
+//    30-cell rows 6, 14, 22, 30); bit 3 reread; bits 5-7 the i-chunk (single
+//    solves: the longest within 256, 512, 768, 1024, 1536, 2048, 4096 or 16384
+//    workgroups; batches 8, 12, 16, 24, 32, 48, 64 or 128 planes); bits 4, 8
+//    and 9 unused.
+//  one iteration: bit 0 the march kernel (set), else for single solves the
+//    flat kernel (bit 3 set) or the direct kernel, for batches the flat
+//    kernel; bits 1-2 bj 1, 2, 4, 8 (flat and direct read 1 as 2); bits 3-4
+//    vec of the march kernel 1, 2, 1, 2 (FP64) or 1, 2, 4, 4 (FP32); bits 5-6
+//    the i-chunk (single solves: about 1024, 2048, 4096 or 8192 workgroups;
+//    batches 2, 4, 8 or 16 planes); bit 7 unused; bit 8 nontemporal; bit 9
+//    xcd_remap of the march kernel (single solves) or the persistent grid
+//    (batches).
 bool decode_gene(uint32_t g, int dtype, int nx, int ny, int nz, bool batch, hj_config& c)
 {
-    static const int kBj[4] = {1, 2, 4, 8}, kBjFused[4] = {14, 6, 4, 8}, kBjNarrow[4] = {14, 6, 22, 30};
+    static const int kBj[4] = {1, 2, 4, 8};
+    static const int kBj62[4] = {4, 6, 8, 14}, kBj64[4] = {4, 6, 8, 12}, kBj30[4] = {6, 14, 22, 30};
     static const int kVec64[4] = {1, 2, 1, 2}, kVec32[4] = {1, 2, 4, 4};
+    static const long long kTwoWg[8] = {256, 512, 768, 1024, 1536, 2048, 4096, 16384};
+    static const int kTwoPlanes[8] = {8, 12, 16, 24, 32, 48, 64, 128};
     c = default_config(dtype);
-    const int b0 = g & 1, b10 = (g >> 10) & 1;
-    if (batch) c.kernel = b0 ? HJ_KERNEL_MARCH : HJ_KERNEL_FLAT;
-    else c.kernel = b0 ? HJ_KERNEL_MARCH : (b10 ? HJ_KERNEL_FLAT : HJ_KERNEL_DIRECT);
-    c.tsteps = (b0 && b10) ? 2 : 1;
-    const int bi = (g >> 1) & 3, vi = (g >> 3) & 3, sel = (g >> 5) & 7;
+    const int b0 = g & 1, bi = (g >> 1) & 3, b3 = (g >> 3) & 1, vi = (g >> 3) & 3;
+    const int sel3 = (g >> 5) & 7, sel2 = (g >> 5) & 3;
+    c.use_graph = 1;
+    c.persistent = 0;
+    c.reread = 0;
+    if ((g >> 10) & 1) {
+        c.kernel = HJ_KERNEL_MARCH;
+        c.tsteps = 2;
+        c.nontemporal = 0;
+        c.xcd_remap = 1;
+        c.reread = b3;
+        if (!b0) {
+            c.vec = 1;
+            c.bj = kBj62[bi];
+        } else if (batch) {
+            c.vec = 4;
+            c.bj = kBj30[bi];
+        } else {
+            c.vec = 2;
+            c.bj = kBj64[bi];
+        }
+        c.ichunk = batch ? kTwoPlanes[sel3] : ichunk_within(c, nx, ny, nz, kTwoWg[sel3]);
+        return config_supported(dtype, c);
+    }
+    c.tsteps = 1;
+    c.nontemporal = (g >> 8) & 1;
+    const int b9 = (g >> 9) & 1;
     c.bj = kBj[bi];
     c.vec = dtype == HJ_F64 ? kVec64[vi] : kVec32[vi];
-    c.nontemporal = (g >> 8) & 1;
-    const bool b9 = (g >> 9) & 1;
-    c.xcd_remap = (!batch || c.tsteps == 2) ? b9 : 0;
-    c.persistent = (batch && c.tsteps == 1) ? b9 : 0;
-    if (c.kernel == HJ_KERNEL_FLAT) {
-        if (c.bj == 1) c.bj = 2;
-        c.vec = 1;
-        c.ichunk = batch ? (1 << sel) : gene_ichunk(sel, c, nx, ny, nz);
-        if (!batch && !config_fits(dtype, c, nx, ny, nz)) {
-            c.kernel = HJ_KERNEL_MARCH;               // fold onto the march kernel
-            c.ichunk = gene_ichunk(sel, c, nx, ny, nz);
-        }
-    } else if (c.kernel == HJ_KERNEL_DIRECT) {
-        if (c.bj == 1) c.bj = 2;
-        c.vec = 1;
-        c.ichunk = 1;
-    } else if (c.tsteps == 2) {
-        c.bj = kBjFused[bi];
-        c.vec = (vi >> 1) ? (batch ? 4 : 2) : 1;
-        if (c.vec == 2 && c.bj == 14) c.bj = 12;
-        if (c.vec == 4) c.bj = kBjNarrow[bi];
-        c.reread = vi & 1;
-        c.ichunk = batch ? (4 << sel) : gene_ichunk(sel, c, nx, ny, nz);
+    c.xcd_remap = 0;
+    if (b0) {
+        c.kernel = HJ_KERNEL_MARCH;
+        if (batch) c.persistent = b9;
+        else c.xcd_remap = b9;
+        c.ichunk = batch ? (2 << sel2) : ichunk_for(c, nx, ny, nz, 1024LL << sel2);
     } else {
-        c.ichunk = batch ? (1 << sel) : gene_ichunk(sel, c, nx, ny, nz);
+        c.kernel = (batch || b3) ? HJ_KERNEL_FLAT : HJ_KERNEL_DIRECT;
+        if (c.bj == 1) c.bj = 2;
+        c.vec = 1;
+        if (c.kernel == HJ_KERNEL_DIRECT) {
+            c.ichunk = 1;
+        } else {
+            if (batch) c.persistent = b9;
+            c.ichunk = batch ? (2 << sel2) : ichunk_for(c, nx, ny, nz, 1024LL << sel2);
+            if (!batch && !config_fits(dtype, c, nx, ny, nz)) {
+                c.kernel = HJ_KERNEL_MARCH;           // a run too wide for the grid: the march kernel
+                c.ichunk = ichunk_for(c, nx, ny, nz, 1024LL << sel2);
+            }
+        }
     }
     return config_supported(dtype, c);
 }
@@ -1157,6 +1192,20 @@ int validate_config(int dtype, const hj_config* c)
 
 // The autotuner's candidates for one grid; cus is the device's CU count
 // (two-iteration chunks are sized to whole waves of resident workgroups).
+// Every configuration a gene names (decode_gene), added to a candidate list,
+// so that the exhaustive search covers the genetic search's space.
+void add_gene_space(std::vector<hj_config>& out, int dtype, int nx, int ny, int nz, bool batch)
+{
+    for (uint32_t g = 0; g < (1u << kGeneBits); ++g) {
+        hj_config x;
+        if (!decode_gene(g, dtype, nx, ny, nz, batch, x)) continue;
+        if (!batch && !config_fits(dtype, x, nx, ny, nz)) continue;
+        bool dup = false;
+        for (const hj_config& y : out) dup = dup || same_config(x, y);
+        if (!dup) out.push_back(x);
+    }
+}
+
 std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch, int cus)
 {
     std::vector<hj_config> out;
@@ -1245,6 +1294,7 @@ std::vector<hj_config> candidates(int dtype, int nx, int ny, int nz, bool batch,
                     }
                 }
     }
+    add_gene_space(out, dtype, nx, ny, nz, batch);
     return out;
 }
 
@@ -2382,6 +2432,13 @@ std::vector<hj_config> batch_candidates(const hj_batch_s* b)
                 c.reread = rr; c.xcd_remap = 1;
                 if (config_supported(dtype, c)) out.push_back(c);
             }
+    std::vector<hj_config> genes;
+    add_gene_space(genes, dtype, 0, 0, 0, true);
+    for (const hj_config& x : genes) {
+        bool dup = false;
+        for (const hj_config& y : out) dup = dup || same_config(x, y);
+        if (!dup && (x.kernel != HJ_KERNEL_FLAT || batch_fits(b, x))) out.push_back(x);
+    }
     return out;
 }
 

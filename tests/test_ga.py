@@ -162,52 +162,60 @@ def test_gene_decoding(lib):
     def dec(dtype, gene, batch=0, shape=(130, 130, 258)):
         assert lib.hj_gene_config(dtype, *shape, batch, gene, ctypes.byref(c)) == 0
         return c.as_dict()
-    # march, bj 4, vec 2, chunk choice 0, non-temporal, no remap
+    two = 1 << 10
+    # one iteration: march, bj 4, vec 2, chunk choice 0, non-temporal, no remap
     d = dec(0, 1 | (2 << 1) | (1 << 3) | (1 << 8))
     assert (d["kernel"], d["bj"], d["vec"], d["nontemporal"], d["xcd_remap"], d["tsteps"]) == (1, 4, 2, 1, 0, 1)
+    assert dec(0, 1 | (1 << 9))["xcd_remap"] == 1
     # every gene names a configuration, for both dtypes, solves and batches
     for dtype in (0, 1):
         for batch in (0, 1):
             for g in range(2 ** 11):
-                d = dec(dtype, g, batch)
-                if batch:
-                    assert d["kernel"] in (1, 2)
-                    if d["tsteps"] == 2:                # two-iteration batches: renumbering, no persistent grid
-                        assert d["kernel"] == 1 and d["persistent"] == 0 and d["ichunk"] == 4 << ((g >> 5) & 7)
-                        assert d["xcd_remap"] == (g >> 9) & 1
-                        assert d["vec"] == (4 if (g >> 4) & 1 else 1)   # batches: narrow rows on bit 4
+                d = dec(dtype, g, batch, shape=(0, 0, 0) if batch else (130, 130, 258))
+                assert d["tsteps"] == (2 if g & two else 1)
+                if d["tsteps"] == 2:
+                    # the settings the exhaustive search keeps for two-iteration passes
+                    assert d["kernel"] == 1 and d["nontemporal"] == 0 and d["xcd_remap"] == 1
+                    assert d["persistent"] == 0 and d["reread"] == (g >> 3) & 1
+                    if batch:
+                        assert d["ichunk"] == (8, 12, 16, 24, 32, 48, 64, 128)[(g >> 5) & 7]
+                        assert d["vec"] == (4 if g & 1 else 1)
                     else:
-                        assert d["tsteps"] == 1 and d["xcd_remap"] == 0
+                        assert d["vec"] == (2 if g & 1 else 1)
+                    # bits 4, 8 and 9 are unused here
+                    assert d == dec(dtype, g ^ (1 << 4) ^ (1 << 8) ^ (1 << 9), batch,
+                                    shape=(0, 0, 0) if batch else (130, 130, 258))
+                else:
+                    assert d["reread"] == 0
+                    if batch:
+                        assert d["kernel"] in (1, 2) and d["xcd_remap"] == 0
+                        assert d["persistent"] == (g >> 9) & 1
+                        assert d["ichunk"] == 2 << ((g >> 5) & 3)
+                    elif d["kernel"] != 1:
+                        assert d["xcd_remap"] == 0 and d["vec"] == 1
     # folded codes: vec code 2 is 1 for FP64 and 4 for FP32; direct reads bj 1 as 2
     assert dec(0, 1 | (2 << 3))["vec"] == 1 and dec(1, 1 | (2 << 3))["vec"] == 4
     assert dec(0, 0)["bj"] == 2 and dec(0, 0)["kernel"] == 0
-    # two iterations per pass: march only, bj codes read as 14, 6, 4, 8; bit 3
-    # reread, bit 4 the 64-cell rows (vec 2), where bj 14 reads as 12
-    d = dec(0, 1 | (1 << 10) | (1 << 3))
-    assert (d["tsteps"], d["vec"], d["bj"], d["reread"]) == (2, 1, 14, 1)
-    d = dec(0, 1 | (1 << 10) | (3 << 3))
-    assert (d["tsteps"], d["vec"], d["bj"], d["reread"]) == (2, 2, 12, 1)
-    assert dec(0, 1 | (1 << 10) | (2 << 3))["reread"] == 0
-    assert [dec(0, 1 | (1 << 10) | (b << 1))["bj"] for b in range(4)] == [14, 6, 4, 8]
-    assert [dec(0, 1 | (1 << 10) | (2 << 3) | (b << 1))["bj"] for b in range(4)] == [12, 6, 4, 8]
-    assert [dec(1, 1 | (1 << 10) | (2 << 3) | (b << 1), batch=1, shape=(0, 0, 0))["bj"]
-            for b in range(4)] == [14, 6, 22, 30]
-    # the 64-cell rows tile a 256-wide interior in 4: the chunks fit 256 workgroups in 4 x 16 x 4
-    assert dec(0, 1 | (1 << 10) | (2 << 3) | (3 << 1))["ichunk"] == 32
-    # their chunks: the longest within 256, 512, ... workgroups (5 x 16 tiles of bj 8 here)
-    fch = [dec(0, 1 | (1 << 10) | (3 << 1) | (sel << 5))["ichunk"] for sel in range(8)]
-    assert fch[:4] == [43, 22, 15, 11]
-    for sel, wg in enumerate((256, 512, 768, 1024, 2048, 4096, 8192, 24576)):
-        assert 80 * -(-128 // fch[sel]) <= wg
-    d = dec(0, 1 << 10)                                 # bit 0 clear, bit 10 set: the flat kernel
+    d = dec(0, 1 << 3)                                  # bit 0 clear, bit 3 set: the flat kernel
     assert (d["kernel"], d["tsteps"], d["bj"]) == (2, 1, 2)
     # a flat run too wide for the grid folds onto the march kernel
-    assert dec(0, (1 << 10) | (3 << 1), shape=(5, 6, 900))["kernel"] == 1
-    # batch: bit 9 is the persistent grid, the chunk is 2^(bits 5-7)
-    d = dec(1, 1 | (1 << 1) | (3 << 5) | (1 << 9), batch=1, shape=(0, 0, 0))
+    assert dec(0, (1 << 3) | (3 << 1), shape=(5, 6, 900))["kernel"] == 1
+    # two iterations: bj codes per row layout
+    assert [dec(0, two | (b << 1))["bj"] for b in range(4)] == [4, 6, 8, 14]
+    assert [dec(0, two | 1 | (b << 1))["bj"] for b in range(4)] == [4, 6, 8, 12]
+    assert [dec(1, two | 1 | (b << 1), batch=1, shape=(0, 0, 0))["bj"] for b in range(4)] == [6, 14, 22, 30]
+    # the 64-cell rows tile a 256-wide interior in 4: bj 8 fits 256 workgroups in 4 x 16 x 4 chunks of 32
+    assert dec(0, two | 1 | (2 << 1))["ichunk"] == 32
+    # their chunks: the longest within 256, 512, ... workgroups (5 x 16 tiles of 62-cell rows, bj 8)
+    fch = [dec(0, two | (2 << 1) | (sel << 5))["ichunk"] for sel in range(8)]
+    assert fch[:4] == [43, 22, 15, 11]
+    for sel, wg in enumerate((256, 512, 768, 1024, 1536, 2048, 4096, 16384)):
+        assert 80 * -(-128 // fch[sel]) <= wg
+    # batch: bit 9 is the persistent grid, the chunk is 2 << (bits 5-6)
+    d = dec(1, 1 | (1 << 1) | (2 << 5) | (1 << 9), batch=1, shape=(0, 0, 0))
     assert (d["kernel"], d["persistent"], d["ichunk"], d["xcd_remap"]) == (1, 1, 8, 0)
     assert dec(1, (2 << 1) | (2 << 5), batch=1, shape=(0, 0, 0))["kernel"] == 2
-    # chunk choices shrink as the workgroup target grows
-    ch = [dec(0, 1 | (2 << 1) | (sel << 5))["ichunk"] for sel in range(8)]
-    assert ch == sorted(ch, reverse=True) and ch[-1] == 1
+    # one-iteration chunk choices shrink as the workgroup target grows
+    ch = [dec(0, 1 | (2 << 1) | (sel << 5))["ichunk"] for sel in range(4)]
+    assert ch == sorted(ch, reverse=True)
     assert lib.hj_gene_config(5, 130, 130, 258, 0, 0, ctypes.byref(c)) == -3
