@@ -198,8 +198,13 @@ def accuracy(w, arrays, p_gpu, hist_gpu, iters: int):
     pref, _, href = oracle.sweep(arrays, iters, w.omega, nthreads=oracle.max_threads())
     ferr = float(np.abs(p_gpu.astype(np.float64) - pref).max() / np.abs(pref).max())
     gerr = float(np.max(np.abs(hist_gpu - href) / href))
-    return {"field_rel_err": ferr, "gosa_rel_err": gerr, "iters_checked": iters,
-            "field_bitwise": bool(np.array_equal(p_gpu.astype(np.float64), pref))}
+    out = {"field_rel_err": ferr, "gosa_rel_err": gerr, "iters_checked": iters,
+           "field_bitwise": bool(np.array_equal(p_gpu.astype(np.float64), pref))}
+    if p_gpu.dtype == np.float32:
+        # FP32 residuals reach the FP32 rounding floor as the solve converges,
+        # far below the FP64 oracle's gosa: reported, not gated
+        out["gosa_gated"] = False
+    return out
 
 
 def whole_grid_accuracy(w, inputs, p_gpu, hist_gpu, iters: int):
@@ -544,7 +549,85 @@ def cpu_baseline_leg(w, arrays, budget_s: float, checks: dict, inputs):
     return cpu_baseline(w, arrays, budget_s), acc
 
 
+def counter_means(run_dir: str, counter: str) -> dict:
+    """Per-kernel mean of one rocprofv3 --pmc counter (KiB per dispatch) over
+    every *counter_collection.csv under run_dir: {kernel: (mean, dispatches)}."""
+    import csv
+    import glob
+    sums, counts = {}, {}
+    for path in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                k = row["Kernel_Name"]
+                sums[k] = sums.get(k, 0.0) + float(row["Counter_Value"])
+                counts[k] = counts.get(k, 0) + 1
+    return {k: (sums[k] / counts[k], counts[k]) for k in sums}
+
+
+def ingest_counters(key: str, kernel: str, fetch_dir: str, write_dir: str, bench_json: str, copy_bytes: int,
+                    per_pass: int = 1) -> dict:
+    """Record the HBM bytes of `kernel` in profiles/traffic.json under `key`:
+    FETCH_SIZE and WRITE_SIZE from two rocprofv3 --pmc runs of the same bench
+    command, each scaled by what the counter read for the library's copy
+    kernel over copy_bytes in that run (the calibration), times per_pass
+    dispatches per pass (the per-instance batch modes launch one kernel per
+    instance). The entry is keyed by the current kernel code and by the
+    configuration the profiled run used (its JSON line in bench_json), so
+    bench.py reports it only while both still hold."""
+    fetch, write = counter_means(fetch_dir, "FETCH_SIZE"), counter_means(write_dir, "WRITE_SIZE")
+    cal = {}
+    for name, tab, full in (("fetch", fetch, copy_bytes / 1024.0), ("write", write, copy_bytes / 1024.0)):
+        copies = [k for k in tab if "copy_kernel" in k]
+        if len(copies) != 1:
+            raise SystemExit("%s run: expected one copy_kernel calibration entry, found %r" % (name, copies))
+        cal[name] = (full / tab[copies[0]][0], tab[copies[0]][0])
+    names = [k for k in fetch if kernel in k and k in write]
+    if len(names) != 1:
+        raise SystemExit("kernel %r matches %r in both runs" % (kernel, names))
+    kname = names[0]
+    fk, nf = fetch[kname]
+    wk, nw = write[kname]
+    fb, wb = fk * 1024 * cal["fetch"][0] * per_pass, wk * 1024 * cal["write"][0] * per_pass
+    with open(bench_json) as f:
+        line = json.loads([ln for ln in f if ln.strip().startswith("{")][-1])
+    if "config" in line and "kernel_config" in line["config"]:
+        cfg = line["config"]["kernel_config"]
+    else:
+        cfg = [v for v in line.values() if isinstance(v, dict) and "config" in v][0]["config"]
+    entry = {"kernel_hash": kernel_hash(), "config": cfg, "kernel": kname, "bytes_per_launch": int(round(fb + wb)),
+             "fetch_bytes": int(round(fb)), "write_bytes": int(round(wb)), "fetch_kib_raw": fk, "write_kib_raw": wk,
+             "dispatches": [nf, nw], "dispatches_per_pass": per_pass,
+             "copy_calibration": {"bytes": copy_bytes, "fetch_kib_raw": cal["fetch"][1],
+                                  "write_kib_raw": cal["write"][1], "fetch_scale": cal["fetch"][0],
+                                  "write_scale": cal["write"][0]}}
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        t = {}
+    t[key] = entry
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(t, f, indent=1, sort_keys=True)
+        f.write("\n")
+    return entry
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--ingest-counters":
+        ig = argparse.ArgumentParser(prog="bench.py --ingest-counters")
+        ig.add_argument("key")
+        ig.add_argument("kernel", help="a substring naming the kernel, e.g. 'wide_kernel<double'")
+        ig.add_argument("fetch_dir")
+        ig.add_argument("write_dir")
+        ig.add_argument("bench_json", help="the JSON line the profiled bench command printed")
+        ig.add_argument("--copy-bytes", type=int, default=1 << 30)
+        ig.add_argument("--per-pass", type=int, default=1)
+        a = ig.parse_args(sys.argv[2:])
+        e = ingest_counters(a.key, a.kernel, a.fetch_dir, a.write_dir, a.bench_json, a.copy_bytes, a.per_pass)
+        print(json.dumps({a.key: e}, indent=1))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)

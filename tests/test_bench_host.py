@@ -44,3 +44,36 @@ def test_roofline_counts_each_array_once_per_pass():
     m = bench.roofline(8, 8_000_000, 2, 0.1, 1.08 * 14 * 8 * 8_000_000)
     assert abs(m["traffic_over_algorithmic"] - 1.08) < 1e-12
     assert abs(m["measured_frac"] - 1.08 * m["frac"]) < 1e-12
+
+
+def _counter_csv(path, rows):
+    import csv
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for d, (k, c, v) in enumerate(rows):
+            w.writerow({"Dispatch_Id": d, "Kernel_Name": k, "Counter_Name": c, "Counter_Value": v})
+
+
+def test_ingest_counters_scales_by_the_copy_calibration(tmp_path, monkeypatch):
+    """Counter bytes are the per-dispatch mean, scaled by what the counter read
+    for the copy kernel over a known size, times the launches per pass; the
+    entry carries the profiled run's configuration and the kernel-code key."""
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    kern = "void hj::wide_kernel<double, 8, false, true>(hj::Grid<double>, ...)"
+    copy = "hj::copy_kernel(unsigned int __vector(4) const*, ...)"
+    # 1 GiB copy: FETCH reads half (64 B per 128 B request), WRITE reads all
+    _counter_csv(str(tmp_path / "f" / "host" / "fetch_counter_collection.csv"),
+                 [(kern, "FETCH_SIZE", 100.0), (kern, "FETCH_SIZE", 300.0), (copy, "FETCH_SIZE", 524288.0)])
+    _counter_csv(str(tmp_path / "w" / "host" / "write_counter_collection.csv"),
+                 [(kern, "WRITE_SIZE", 50.0), (kern, "WRITE_SIZE", 50.0), (copy, "WRITE_SIZE", 1048576.0)])
+    cfg = {"kernel": 1, "bj": 8, "vec": 2, "ichunk": 32, "tsteps": 2}
+    (tmp_path / "run.json").write_text("noise\n" + __import__("json").dumps({"config": {"kernel_config": cfg}}) + "\n")
+    e = bench.ingest_counters("medium_f64", "wide_kernel<double, 8", str(tmp_path / "f"), str(tmp_path / "w"),
+                              str(tmp_path / "run.json"), 1 << 30, per_pass=3)
+    assert e["fetch_bytes"] == 200 * 1024 * 2 * 3 and e["write_bytes"] == 50 * 1024 * 3
+    assert e["bytes_per_launch"] == e["fetch_bytes"] + e["write_bytes"]
+    assert e["config"] == cfg and e["kernel_hash"] == bench.kernel_hash() and e["dispatches"] == [2, 2]
+    assert bench.load_traffic("medium_f64", cfg) == e["bytes_per_launch"]
+    assert bench.load_traffic("medium_f64", dict(cfg, bj=4)) is None
