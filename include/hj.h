@@ -111,20 +111,27 @@ typedef struct hj_batch_s* hj_batch;
 
 /* ---- single solve ------------------------------------------------------ */
 
-/* Bytes of device memory a solve of this shape needs (for hj_attach). */
+/* Bytes of device memory a solve of this shape needs (for hj_attach).
+ * Paper section 3.3 / section 4: the arrays get a GPU-side area of their own
+ * that the transfers fill, so no transfer happens implicitly in the loop. */
 int hj_slab_bytes(int dtype, int nx, int ny, int nz, unsigned long long* bytes);
 
-/* Create a solve that owns its device memory. stream: a hipStream_t, or
- * NULL for a library-created non-blocking stream. */
+/* Create a solve that owns its device memory (the GPU-side area of paper
+ * sections 3.3 and 4). stream: a hipStream_t, or NULL for a library-created
+ * non-blocking stream. */
 int hj_create(hj_solver* out, int dtype, int nx, int ny, int nz, void* stream);
 
 /* Create a solve on caller-owned device memory of at least hj_slab_bytes
- * bytes, 256-byte aligned (e.g. a torch uint8 tensor). The caller keeps it
+ * bytes, 256-byte aligned (e.g. a torch uint8 tensor): the same GPU-side
+ * area (paper section 3.3), supplied by the caller. The caller keeps it
  * alive and unused until hj_destroy. */
 int hj_attach(hj_solver* out, int dtype, int nx, int ny, int nz, void* device_slab,
               unsigned long long slab_bytes, void* stream);
 
-/* Upload one input field from a dense host array in the handle's dtype
+/* Paper sections 3.3 and 4: what the CPU defines and the GPU reads is sent
+ * once, before the GPU work, at the outermost level (a data copy batched
+ * over the loop, not a transfer per iteration).
+ * Upload one input field from a dense host array in the handle's dtype
  * (hj_upload) or in FP64 (hj_upload_f64, rounded to nearest even for HJ_F32
  * handles). Uploading HJ_P also resets the ping-pong partner to p and makes
  * p current. HJ_WRK2 cannot be uploaded (HJ_ERR_ARG). Synchronous. A pinned
@@ -135,7 +142,8 @@ int hj_attach(hj_solver* out, int dtype, int nx, int ny, int nz, void* device_sl
 int hj_upload(hj_solver h, int field, const void* host_src);
 int hj_upload_f64(hj_solver h, int field, const double* host_src);
 
-/* Download a field into a dense host array of the handle's dtype. HJ_P and
+/* Paper sections 3.3 and 4: results come back once, after all the GPU work.
+ * Download a field into a dense host array of the handle's dtype. HJ_P and
  * HJ_WRK2 both return the current field (the last sweep's wrk2 once any
  * sweep has run). Synchronous. Pinned host memory is written directly, as
  * for hj_upload. */
@@ -158,13 +166,17 @@ int hj_snapshot(hj_solver h, void* host_dst);
  * pending. hj_destroy also waits. */
 int hj_snapshot_wait(hj_solver h);
 
-/* Run n_iter Jacobi iterations with relaxation omega on the resident arrays.
+/* The offloaded loop: the Himeno workload's Jacobi iteration (paper section
+ * 5.1.1), run on arrays already resident (section 3.3: present data, no
+ * transfer inside the loop; only the FP64 gosa values come back).
+ * Run n_iter Jacobi iterations with relaxation omega on the resident arrays.
  * gosa_last (nullable) receives the last iteration's gosa, gosa_hist
  * (nullable, n_iter doubles) every iteration's, each computed from the field
  * before that iteration's update. Synchronous. n_iter == 0 is a no-op. */
 int hj_sweep(hj_solver h, int n_iter, double omega, double* gosa_last, double* gosa_hist);
 
-/* As hj_sweep, but only enqueued on the handle's stream: the per-iteration
+/* Paper section 5.1.1 and 3.3 as for hj_sweep.
+ * As hj_sweep, but only enqueued on the handle's stream: the per-iteration
  * gosa goes to dev_gosa_hist (nullable device pointer, n_iter doubles). */
 int hj_sweep_async(hj_solver h, int n_iter, double omega, double* dev_gosa_hist);
 
@@ -189,10 +201,15 @@ int hj_sweep_async(hj_solver h, int n_iter, double omega, double* dev_gosa_hist)
 #define HJ_NOALLOC_SCRATCH_DOUBLES 524288
 int hj_sweep_noalloc(hj_solver h, int n_iter, double omega, double* dev_gosa_hist);
 
-/* gosa of the current field, without updating it. Synchronous. */
+/* gosa of the current field, without updating it: the residual sum of the
+ * Jacobi iteration of paper section 5.1.1 (the paper names the workload; the
+ * sum is this library's reading, stated at the top of this file).
+ * Synchronous. */
 int hj_residual(hj_solver h, double* gosa);
 
-/* The configuration the next sweep runs with: the library default, the
+/* The knobs of paper section 3.2's tuning list (coalesced access, use of the
+ * memory levels, occupancy, parallel granularity) as this kernel's
+ * configuration. The configuration the next sweep runs with: the library default, the
  * tuning cache's entry for this problem, the last autotune winner or the
  * last hj_set_config. The default of a new solve is the two-iteration
  * kernel on 64-cell rows (kernel HJ_KERNEL_MARCH, bj 8, vec 2, tsteps 2,
@@ -205,7 +222,10 @@ int hj_residual(hj_solver h, double* gosa);
 int hj_get_config(hj_solver h, hj_config* out);
 int hj_set_config(hj_solver h, const hj_config* cfg);
 
-/* Measure the candidate configurations on this handle's arrays and keep the
+/* Paper section 4: candidates are measured on the real program and the
+ * fastest measured one is the solution; the result is checked against a
+ * reference (there the CPU, with PCAST) before it is used.
+ * Measure the candidate configurations on this handle's arrays and keep the
  * fastest one whose field is bitwise equal to the reference configuration's
  * after the same sweeps. The solve's state (p) is restored afterwards.
  * With the environment variable HJ_TUNE_CACHE=<file>, the winner is recorded
@@ -246,7 +266,8 @@ int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long l
                    double pm, int n_sweeps, int repeats, hj_config* best, double* best_ms,
                    int* evaluations);
 
-/* The configuration a gene names for this problem; every gene names one, and
+/* Paper section 4: a gene of one bit per decision.
+ * The configuration a gene names for this problem; every gene names one, and
  * every one of them is among the configurations hj_autotune (or, for batch
  * != 0, hj_batch_autotune) measures, so both searches cover the same space.
  * bit 10: two iterations per pass (1) or one (0).
@@ -269,7 +290,8 @@ int hj_autotune_ga(hj_solver h, int population, int generations, unsigned long l
  * as the march kernel. Returns HJ_ERR_ARG for an unknown dtype. Host only. */
 int hj_gene_config(int dtype, int nx, int ny, int nz, int batch, unsigned gene, hj_config* out);
 
-/* The same genetic search with the time of every gene given by a table
+/* Paper sections 4 and 5.1.2 (the search itself, without a GPU).
+ * The same genetic search with the time of every gene given by a table
  * (time_of_gene[g] in seconds for g < 2^gene_bits, gene_bits <= 20). Host
  * only: no GPU is used. history (nullable) receives the genes of every
  * generation, [generations][population]. */
@@ -277,10 +299,11 @@ int hj_ga_run(int gene_bits, int population, int generations, unsigned long long
               double pm, const double* time_of_gene, unsigned* best_gene, double* best_time,
               unsigned* history, int* evaluations);
 
-/* Wait for all work queued on the handle's stream. */
+/* Runtime plumbing (no passage of the paper): wait for all work queued on
+ * the handle's stream. */
 int hj_sync(hj_solver h);
 
-/* The HIP stream used by the handle (a hipStream_t). */
+/* Runtime plumbing: the HIP stream used by the handle (a hipStream_t). */
 int hj_get_stream(hj_solver h, void** stream);
 
 /* Wait for the handle's queued work, then release it: its device memory
@@ -290,7 +313,10 @@ int hj_destroy(hj_solver h);
 
 /* ---- batch of independent solves ---------------------------------------- */
 
-/* n >= 1 independent solves (the same operator, each with its own shape
+/* Not in the paper: many independent solves of paper section 5.1.1's
+ * workload, each resident as section 3.3 prescribes, advanced together so
+ * that small grids still fill the GPU.
+ * n >= 1 independent solves (the same operator, each with its own shape
  * nx[t] x ny[t] x nz[t], every side >= 3, else HJ_ERR_SHAPE naming the
  * instance) held in one device slab the batch owns, and advanced together:
  * each pass is one launch over a flattened list of every instance's tiles
@@ -300,7 +326,8 @@ int hj_destroy(hj_solver h);
 int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* ny,
                     const int* nz, void* stream);
 
-/* Upload / download one field of instance inst (0 <= inst < n) as hj_upload
+/* Paper sections 3.3 and 4, per instance (as hj_upload / hj_download).
+ * Upload / download one field of instance inst (0 <= inst < n) as hj_upload
  * / hj_upload_f64 / hj_download do for a single solve (dense host array of
  * that instance's shape; HJ_P also resets the partner; HJ_WRK2 cannot be
  * uploaded). Synchronous. */
@@ -308,20 +335,23 @@ int hj_batch_upload(hj_batch b, int inst, int field, const void* host_src);
 int hj_batch_upload_f64(hj_batch b, int inst, int field, const double* host_src);
 int hj_batch_download(hj_batch b, int inst, int field, void* host_dst);
 
-/* n_iter iterations of every instance (HJ_ERR_STATE until every input field
+/* Paper section 5.1.1's iteration on every instance (as hj_sweep).
+ * n_iter iterations of every instance (HJ_ERR_STATE until every input field
  * of every instance is uploaded). gosa_last (nullable, n doubles),
  * gosa_hist (nullable, n_iter*n doubles, [iteration][instance]), each
  * instance's sum in a fixed order. Synchronous. */
 int hj_batch_sweep(hj_batch b, int n_iter, double omega, double* gosa_last, double* gosa_hist);
 
-/* gosa of every instance's current field (n doubles), no update. */
+/* gosa of every instance's current field (n doubles), no update (as
+ * hj_residual). */
 int hj_batch_residual(hj_batch b, double* gosa);
 int hj_batch_get_config(hj_batch b, hj_config* out);
 /* Any supported configuration but the direct kernel; a flat kernel must fit
  * every instance (else HJ_ERR_ARG). xcd_remap and reread are kept for
  * two-iteration passes (tsteps 2, not persistent) and cleared otherwise. */
 int hj_batch_set_config(hj_batch b, const hj_config* cfg);
-/* As hj_autotune, over the batch's candidates (one configuration for all
+/* Paper section 4 (as hj_autotune).
+ * As hj_autotune, over the batch's candidates (one configuration for all
  * instances); the parity gate compares every instance's current field, and
  * the cache line is keyed by a hash of the instance shapes. */
 int hj_batch_autotune(hj_batch b, int n_sweeps, int repeats, hj_config* best, double* best_ms);
@@ -338,7 +368,8 @@ int hj_batch_destroy(hj_batch b);
 const char* hj_status_string(int status);
 const char* hj_last_error(void);
 
-/* Device time, in milliseconds, of the last hj_sweep / hj_batch_sweep on this
+/* Measurement (paper section 3.2: how well a loop does on the GPU is known
+ * only by measuring it). Device time, in milliseconds, of the last hj_sweep / hj_batch_sweep on this
  * thread, measured with HIP events around the launched work. */
 double hj_last_sweep_ms(void);
 
