@@ -22,9 +22,10 @@
 //    the first iteration of a tile and its halo goes to a second LDS ring
 //    and the second is computed from it, so the coefficient arrays are read
 //    once per two iterations; neighbouring tiles run on the same XCD, so
-//    their shared halo reads hit its L2; the FP32 kernel with 64-cell rows
-//    loads every plane two steps before it is used (unconditional loads, so
-//    the compiler waits for nothing newer), the FP64 one a step ahead;
+//    their shared halo reads hit its L2; the FP32 single-solve kernels load
+//    every plane one or two steps before it is used (unconditional loads, so
+//    the compiler waits for nothing newer), the FP64 ones a step ahead,
+//    waiting for those loads within the step;
 //  * the gosa partial of each tile is reduced in registers (64-lane xor
 //    butterfly) and LDS, then written to its own slot, and a second kernel
 //    sums the slots in a fixed order: the result does not depend on timing.
@@ -403,18 +404,20 @@ __device__ __forceinline__ T oload(const T* base, unsigned off)
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Steps of prefetch of the two-iteration tiles (0: the synchronous tiles;
-// PD > 0: tile2_prefetch): two for the FP32 single-solve kernels. FP64
-// cannot hold the extra register set. The batch kernels keep the synchronous
-// tiles: on batch64 the prefetching one lost 9% (FP32, two steps) and the
-// one-step form 9% (FP32) and 8% (FP64); with small ragged grids more lanes
-// load clamped addresses, and the chunks' prologues and ends weigh more.
+// PD > 0: tile2_prefetch) for the FP32 single-solve kernels: two where a
+// workgroup of `waves` waves (asking for at least min_waves waves per SIMD)
+// leaves each wave the 168 registers of three waves per SIMD, one where it
+// leaves 128 (the four register sets of two steps do not fit there). FP64
+// cannot hold the extra register sets and keeps the synchronous tile. The
+// batch kernels keep the synchronous tiles too: on batch64 the prefetching
+// one lost 9% (FP32, two steps) and the one-step form 9% (FP32) and 8%
+// (FP64); with small ragged grids more lanes load clamped addresses, and the
+// chunks' prologues and ends weigh more.
 template <typename T>
-constexpr int kPrefetchSingle = sizeof(T) == 4 ? 2 : 0;
-
-// Whether a workgroup of `waves` waves (asking for at least min_waves waves
-// per SIMD) leaves each wave the 168 registers of three waves per SIMD, which
-// the prefetching tile's whole-round form needs.
-constexpr bool rounds_ok(int waves, int min_waves) { return waves <= 12 && min_waves <= 3; }
+constexpr int prefetch_single(int waves, int min_waves)
+{
+    return sizeof(T) != 4 ? 0 : (waves <= 12 && min_waves <= 3) ? 2 : 1;
+}
 
 // A thread's first-iteration cell in a two-iteration tile whose p0 tile
 // starts at (j0-2, k0-2): grid cell (j, k), its place (rho, c) in the p0 tile
@@ -436,13 +439,14 @@ struct TileCell {
 // rounds of PD+2 steps, so every set is in the same registers at the loop's
 // back edge (no set is copied there, which would make the copy wait for every
 // load in flight); steps past the chunk's last plane read clamped planes and
-// neither store nor sum anything. This form (ROUNDS) takes more registers;
-// workgroups of more than 12 waves keep the earlier one, PD+1 sets and a copy
-// of the previous plane's coefficients, with the march ending at any step.
+// neither store nor sum anything. Measured against PD+1 sets with a copy of
+// the previous plane's (the copies the allocator then made at the back edge
+// each waited for every outstanding load): large_f32 153.3 -> 155.5 GLUPS
+// (two steps), huge_f32 149.7 -> 151.5 (one step, 16-wave workgroups).
 // The p0 tile is fetched as a flat array (two cells per thread). Byte offsets
 // within a plane are 32-bit: a plane must hold fewer than 2^32 bytes
 // (plane32_ok).
-template <typename T, typename Lds, bool NT, bool KEEP, int PD, bool ROUNDS>
+template <typename T, typename Lds, bool NT, bool KEEP, int PD>
 __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0, int k0, const TileCell& tc, int ib,
                                                int ie, Lds& sm, double& acc1, double& acc2)
 {
@@ -491,9 +495,8 @@ __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0
 
     const int i_lo = ib - 1, i_hi = ie;                    // first-iteration planes
     static_assert(PD == 1 || PD == 2, "prefetch distance");
-    constexpr int NS = ROUNDS ? PD + 2 : PD + 1;           // register sets
+    constexpr int NS = PD + 2;                             // register sets
     T ps[NS][2], cs[NS][NCOEF];
-    T kp[ROUNDS ? 1 : NCOEF];                              // the previous plane's set (not ROUNDS)
     for (int ii = i_lo - 1; ii <= i_lo + 1; ++ii) {
         fetch(ii, ps[0]);
         put(ii, ps[0]);
@@ -506,10 +509,7 @@ __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0
     // the first step's second iteration (plane i_lo-1) has no output: its set
     // only needs defined values
 #pragma unroll
-    for (int q = 0; q < NCOEF; ++q) {
-        if constexpr (ROUNDS) cs[NS - 1][q] = T(0);
-        else kp[q] = T(0);
-    }
+    for (int q = 0; q < NCOEF; ++q) cs[NS - 1][q] = T(0);
     // without KEEP the own cell's coefficients of plane i-1 are loaded again
     // at the start of each step
     T rk[KEEP ? 1 : NCOEF];
@@ -584,39 +584,19 @@ __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0
             const double d = (double)ss;
             acc2 += d * d;
         }
-        if constexpr (!ROUNDS && KEEP) {
-#pragma unroll
-            for (int q = 0; q < NCOEF; ++q) kp[q] = cur[q];
-        }
     };
 
     // step number K of a round computes with set K, loads into set K+PD and
-    // (ROUNDS) takes the second iteration's coefficients from set K-1 (mod NS)
+    // takes the second iteration's coefficients from set K-1 (mod NS)
     auto stepk = [&](auto kc, int i) {
         constexpr int K = decltype(kc)::value;
-        if constexpr (ROUNDS)
-            step(i, cs[K % NS], cs[(K + PD) % NS], cs[(K + NS - 1) % NS], ps[(K + PD) % NS], ps[K % NS]);
-        else
-            step(i, cs[K % NS], cs[(K + PD) % NS], kp, ps[(K + PD) % NS], ps[K % NS]);
+        step(i, cs[K % NS], cs[(K + PD) % NS], cs[(K + NS - 1) % NS], ps[(K + PD) % NS], ps[K % NS]);
     };
-    if constexpr (ROUNDS) {
-        for (int i = i_lo; i <= i_hi; i += NS) {
-            stepk(std::integral_constant<int, 0>{}, i);
-            stepk(std::integral_constant<int, 1>{}, i + 1);
-            stepk(std::integral_constant<int, 2>{}, i + 2);
-            if constexpr (NS > 3) stepk(std::integral_constant<int, 3>{}, i + 3);
-        }
-    } else {
-        for (int i = i_lo;;) {
-            stepk(std::integral_constant<int, 0>{}, i);
-            if (++i > i_hi) break;
-            stepk(std::integral_constant<int, 1>{}, i);
-            if (++i > i_hi) break;
-            if constexpr (NS > 2) {
-                stepk(std::integral_constant<int, 2>{}, i);
-                if (++i > i_hi) break;
-            }
-        }
+    for (int i = i_lo; i <= i_hi; i += NS) {
+        stepk(std::integral_constant<int, 0>{}, i);
+        stepk(std::integral_constant<int, 1>{}, i + 1);
+        stepk(std::integral_constant<int, 2>{}, i + 2);
+        if constexpr (NS > 3) stepk(std::integral_constant<int, 3>{}, i + 3);
     }
 }
 
@@ -851,7 +831,7 @@ __device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, i
         fused_tile<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
     } else {
         const int k0 = 1 + kt * FusedLds<T, BJ, W>::TK, j0 = 1 + jt * BJ;
-        tile2_prefetch<T, FusedLds<T, BJ, W>, NT, KEEP, PF, rounds_ok(fused_threads<BJ, W>() / kWave, fused_min_waves<BJ, W>())>(
+        tile2_prefetch<T, FusedLds<T, BJ, W>, NT, KEEP, PF>(
             g, omega, j0, k0, fused_cell<BJ, W>(j0, k0), ib, ie, sm,
                                                            acc1, acc2);
     }
@@ -873,7 +853,8 @@ __global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fu
     const int kt = L % kt_n;
     const int jt = (L / kt_n) % jt_n;
     const int ic = L / (kt_n * jt_n);
-    fused_block<T, BJ, W, NT, KEEP, kPrefetchSingle<T>>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
+    fused_block<T, BJ, W, NT, KEEP, prefetch_single<T>(fused_threads<BJ, W>() / kWave, fused_min_waves<BJ, W>())>(
+        g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
 }
 
 // Two iterations over every instance of a batch: one workgroup per tile of
@@ -1142,7 +1123,7 @@ __device__ __forceinline__ void wide_block(const Grid<T>& g, T omega, int kt, in
         wide_tile_sync<T, BJ, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
     } else {
         const int k0 = 1 + kt * kWave, j0 = 1 + jt * BJ;
-        tile2_prefetch<T, WideLds<T, BJ>, NT, KEEP, PF, rounds_ok(BJ + 3, 1)>(g, omega, j0, k0, wide_cell<BJ>(j0, k0), ib, ie, sm, acc1,
+        tile2_prefetch<T, WideLds<T, BJ>, NT, KEEP, PF>(g, omega, j0, k0, wide_cell<BJ>(j0, k0), ib, ie, sm, acc1,
                                                        acc2);
     }
     acc1 = block_sum<BJ + 3>(acc1, sm.red);
@@ -1161,7 +1142,7 @@ __global__ __launch_bounds__(kWave * (BJ + 3)) void wide_kernel(Grid<T> g, T ome
     const int kt = L % kt_n;
     const int jt = (L / kt_n) % jt_n;
     const int ic = L / (kt_n * jt_n);
-    wide_block<T, BJ, NT, KEEP, kPrefetchSingle<T>>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
+    wide_block<T, BJ, NT, KEEP, prefetch_single<T>(BJ + 3, 1)>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
 }
 
 template <typename T, int BJ, bool NT, bool KEEP>
