@@ -74,7 +74,8 @@ def read_log(path):
     with open(path) as f:
         for r in csv.reader(f):
             rows.append(dict(kernel=int(r[5]), bj=int(r[6]), vec=int(r[7]), ichunk=int(r[8]),
-                             nontemporal=int(r[9]), ms=float(r[12]), verdict=r[13], tsteps=int(r[14])))
+                             nontemporal=int(r[9]), xcd_remap=int(r[10]), persistent=int(r[11]), ms=float(r[12]),
+                             verdict=r[13], tsteps=int(r[14]), reread=int(r[15])))
     return rows
 
 
@@ -190,3 +191,30 @@ def test_async_sweeps_cycle_more_graphs_than_the_cache_holds():
         p_sync = s.download("p")
     assert np.array_equal(p_async, p_sync)
     assert np.array_equal(p_sync, oracle.sweep(f, sum(counts), 0.8, nthreads=4)[0])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_exhaustive_search_measures_every_gene(dtype, tmp_path, monkeypatch):
+    """Both searches cover one space: every configuration an 11-bit gene names
+    for this grid (hj_gene_config) is among those the exhaustive search
+    measures (its tuning log)."""
+    import ctypes
+    log = tmp_path / "tune.csv"
+    monkeypatch.setenv("HJ_TUNE_LOG", str(log))
+    lib = hj.load()
+    lib.hj_gene_config.argtypes = [ctypes.c_int] * 5 + [ctypes.c_uint, ctypes.POINTER(hj.Config)]
+    code = hj.F64 if dtype == "f64" else hj.F32
+    keys = ("kernel", "bj", "vec", "ichunk", "nontemporal", "xcd_remap", "persistent", "tsteps", "reread")
+    genes = set()
+    for g in range(2 ** 11):
+        c = hj.Config()
+        assert lib.hj_gene_config(code, *SHAPE, 0, g, ctypes.byref(c)) == 0
+        genes.add(tuple(c.as_dict()[k] for k in keys))
+    f = inputs.fields(2002, SHAPE)
+    with hj.Solver(dtype, SHAPE) as s:
+        s.upload_all(f)
+        say("exhaustive log", dtype)
+        s.autotune(n_sweeps=2, repeats=1)
+    measured = {tuple(r[k] for k in keys) for r in read_log(log)}
+    missing = genes - measured
+    assert not missing, sorted(missing)[:5]
