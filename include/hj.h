@@ -197,7 +197,12 @@ int hj_sweep_async(hj_solver h, int n_iter, double omega, double* dev_gosa_hist)
  * uploaded. Every call on a GPU shares that GPU's array: calls whose work
  * overlaps on one GPU (other streams, other threads) race and must be
  * ordered by the caller. Nothing needs clearing between calls (each tile
- * writes its own slot before it is read). */
+ * writes its own slot before it is read). Captured into a caller's graph,
+ * the call records launches between the two field buffers as they stand at
+ * capture time; each launch swaps them, so a replay continues the solve
+ * only if the call makes an even number of launches (n_iter a multiple of 4
+ * with two iterations per pass, even with one); the handle's own record of
+ * which buffer holds the field advances once, at the call. */
 #define HJ_NOALLOC_SCRATCH_DOUBLES 524288
 int hj_sweep_noalloc(hj_solver h, int n_iter, double omega, double* dev_gosa_hist);
 
