@@ -107,3 +107,42 @@ def test_noalloc_refuses_partials_beyond_its_array(lib):
         assert rc == -1 and b"NULL" in lib.hj_last_error()
     finally:
         _ok(lib, lib.hj_destroy(h), "hj_destroy")
+
+
+def test_noalloc_captured_in_a_graph_and_replayed(lib):
+    """The allocation-free call captured into a caller's HIP graph (torch's
+    graph capture on the handle's stream) and replayed three times, with
+    downloads between the replays: after replay r the FP64 field equals the
+    oracle's after 4r iterations bitwise, and the gosa the replay wrote equals
+    the oracle's history for those iterations. Four iterations are two
+    two-iteration launches, so the field returns to its buffer each time."""
+    shape, n, omega = (34, 36, 70), 4, 0.8
+    f = inputs.fields(11, shape)
+    stream = torch.cuda.Stream()
+    h = H()
+    _ok(lib, lib.hj_create(ctypes.byref(h), hj.F64, *shape, ctypes.c_void_p(stream.cuda_stream)), "hj_create")
+    try:
+        for name in inputs.INPUTS:
+            a = np.ascontiguousarray(f[name], dtype=np.float64)
+            _ok(lib, lib.hj_upload_f64(h, inputs.FIELD_ID[name], a.ctypes.data), "hj_upload_f64")
+        c = hj.Config()
+        _ok(lib, lib.hj_get_config(h, ctypes.byref(c)), "hj_get_config")
+        assert c.tsteps == 2
+        dev = torch.zeros(n, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        say("capture hj_sweep_noalloc", shape, n)
+        with torch.cuda.graph(g, stream=stream):
+            _ok(lib, lib.hj_sweep_noalloc(h, n, ctypes.c_double(omega), ctypes.c_void_p(dev.data_ptr())),
+                "hj_sweep_noalloc (captured)")
+        _, _, href = oracle.sweep(f, 3 * n, omega, nthreads=4)
+        for r in range(1, 4):
+            say("replay", r)
+            g.replay()
+            torch.cuda.synchronize()
+            p = _download(lib, h, hj.F64, shape)
+            pref = oracle.sweep(f, r * n, omega, nthreads=4)[0]
+            assert np.array_equal(p, pref), (r, field_err(p, pref))
+            assert gosa_err(dev.cpu().numpy(), href[(r - 1) * n:r * n]) <= F64_GOSA_RTOL, r
+    finally:
+        _ok(lib, lib.hj_destroy(h), "hj_destroy")
