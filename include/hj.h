@@ -113,7 +113,10 @@ typedef struct hj_batch_s* hj_batch;
 
 /* Bytes of device memory a solve of this shape needs (for hj_attach).
  * Paper section 3.3 / section 4: the arrays get a GPU-side area of their own
- * that the transfers fill, so no transfer happens implicitly in the loop. */
+ * that the transfers fill, so no transfer happens implicitly in the loop.
+ * The area holds the 14 fields (rows padded to 128-byte lines) and, after
+ * them, a compact copy of the coefficients on the k tile edges (12 arrays x
+ * nx x ceil((nz-2)/64) x ny x 2 elements) that hj_upload fills. */
 int hj_slab_bytes(int dtype, int nx, int ny, int nz, unsigned long long* bytes);
 
 /* Create a solve that owns its device memory (the GPU-side area of paper

@@ -96,6 +96,10 @@ struct Layout {
     int nx = 0, ny = 0, nz = 0, esz = 0, A = 0;
     long long P = 0, S = 0;
     size_t field_bytes = 0, field_stride = 0, slab_bytes = 0;
+    // A single solve's slab also holds the side array of the 64-cell-row
+    // tiles (side_index) after its fields; a batch instance holds the fields only.
+    size_t fields_bytes = 0, side_bytes = 0;
+    int side_kt = 0;
 };
 
 size_t stagger_bytes()
@@ -122,7 +126,10 @@ bool make_layout(int dtype, int nx, int ny, int nz, Layout& L)
     if (bytes > (long double)(1ULL << 46)) return false;
     L.field_bytes = (size_t)nx * (size_t)L.S * (size_t)L.esz;
     L.field_stride = (L.field_bytes + 65535) / 65536 * 65536 + stagger_bytes();
-    L.slab_bytes = (size_t)HJ_NFIELDS * L.field_stride;
+    L.fields_bytes = (size_t)HJ_NFIELDS * L.field_stride;
+    L.side_kt = kt64(nz);
+    L.side_bytes = ((size_t)NCOEF * nx * L.side_kt * ny * 2 * L.esz + 255) / 256 * 256;
+    L.slab_bytes = L.fields_bytes + L.side_bytes;
     return true;
 }
 
@@ -855,6 +862,7 @@ struct hj_solver_s {
     char* field(int q) const { return slab + (size_t)q * L.field_stride; }
     // element (0,0,0) of field q
     char* origin(int q) const { return field(q) + (size_t)(L.A - 1) * L.esz; }
+    char* side() const { return slab + L.fields_bytes; }
 
     template <typename T>
     Grid<T> grid(int par) const
@@ -864,6 +872,8 @@ struct hj_solver_s {
         g.src = reinterpret_cast<const T*>(origin(par ? HJ_WRK2 : HJ_P));
         g.dst = reinterpret_cast<T*>(origin(par ? HJ_P : HJ_WRK2));
         g.nx = L.nx; g.ny = L.ny; g.nz = L.nz; g.P = L.P; g.S = L.S;
+        g.side = reinterpret_cast<const T*>(side());
+        g.side_kt = L.side_kt;
         return g;
     }
 
@@ -1422,6 +1432,19 @@ int solver_upload(hj_solver h, int field, const void* src, bool src_f64)
             h->parity = 0;
         } else {
             copy_in(h->L, h->field(field), src, src_f64, h->stream);
+            // the coefficient's halo columns into the side array
+            const Layout& L = h->L;
+            const int q = field - HJ_A0;
+            const size_t blk = (size_t)L.nx * L.side_kt * L.ny * 2;
+            if (h->dtype == HJ_F64)
+                HIPCHK(launch_side_gather<double>(reinterpret_cast<const double*>(h->origin(field)),
+                                                  reinterpret_cast<double*>(h->side()) + q * blk, L.nx, L.ny,
+                                                  L.nz, L.P, L.S, h->stream));
+            else
+                HIPCHK(launch_side_gather<float>(reinterpret_cast<const float*>(h->origin(field)),
+                                                 reinterpret_cast<float*>(h->side()) + q * blk, L.nx, L.ny, L.nz,
+                                                 L.P, L.S, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
         }
         h->uploaded |= 1u << field;
         return HJ_OK;
@@ -2138,7 +2161,7 @@ int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* n
                 return set_err(HJ_ERR_SHAPE, "instance %d: invalid shape %dx%dx%d", t, nx[t], ny[t], nz[t]);
             }
             b->off[t] = total;
-            total += b->L[t].slab_bytes;
+            total += b->L[t].fields_bytes;
         }
         b->slab_bytes = total;
         b->cfg = batch_default(dtype);

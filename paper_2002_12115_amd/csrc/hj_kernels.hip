@@ -255,7 +255,7 @@ template <typename T, int BJ, int W, bool NT, bool KEEP>
 hipError_t fused_go(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                     hipStream_t st)
 {
-    if (!plane32_ok((int)sizeof(T), g.ny, g.nz)) return hipErrorInvalidValue;  // 32-bit offsets (FP32)
+    if (!plane32_ok((int)sizeof(T), g.ny, g.nz)) return hipErrorInvalidValue;  // 32-bit plane offsets
     const TileCounts t = tile_counts(c, g.nx, g.ny, g.nz);
     const long long nb = t.tiles();
     if (nb <= 0) return hipSuccess;
@@ -279,7 +279,9 @@ hipError_t fused_batch_go(const hj_config& c, const Instance<T>* inst, const int
 template <typename T, int BJ, bool NT, bool KEEP>
 hipError_t wide_go(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2, hipStream_t st)
 {
-    if (!plane32_ok((int)sizeof(T), g.ny, g.nz)) return hipErrorInvalidValue;  // 32-bit offsets (FP32)
+    if (!plane32_ok((int)sizeof(T), g.ny, g.nz)) return hipErrorInvalidValue;  // 32-bit plane offsets
+    // the prefetching form reads the halo columns' coefficients from the side array
+    if (prefetch_wide<T>(BJ) > 0 && (!g.side || g.side_kt != kt64(g.nz))) return hipErrorInvalidValue;
     const TileCounts t = tile_counts(c, g.nx, g.ny, g.nz);
     const long long nb = t.tiles();
     if (nb <= 0) return hipSuccess;
@@ -459,6 +461,25 @@ hipError_t launch_finalize(const double* part, long long stride, int n, const in
                        seg_begin, nseg, out);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_side_gather(const T* coef, T* side, int nx, int ny, int nz, long long P, long long S,
+                              hipStream_t st)
+{
+    const int ktn = kt64(nz);
+    const long long n = (long long)nx * ktn * ny * 2;
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((side_gather_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, st, coef, side, nx, ny, nz, P, S,
+                       ktn);
+    return hipGetLastError();
+}
+
+template hipError_t launch_side_gather<double>(const double*, double*, int, int, int, long long, long long,
+                                               hipStream_t);
+template hipError_t launch_side_gather<float>(const float*, float*, int, int, int, long long, long long,
+                                              hipStream_t);
 
 hipError_t launch_copy(void* dst, const void* src, unsigned long long bytes, hipStream_t st)
 {

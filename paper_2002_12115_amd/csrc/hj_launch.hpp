@@ -41,12 +41,12 @@ inline long long pitch_of(int esz, int nz)
     return (A + nz + 4 + A - 1) / A * A;
 }
 
-// The FP32 two-iteration kernels address a plane with 32-bit byte offsets: a
-// plane (ny rows of the pitch) must hold fewer than 2^32 bytes. The FP64
-// kernels use 64-bit offsets.
+// The prefetching two-iteration kernels address a plane with 32-bit byte
+// offsets: a plane (ny rows of the pitch) must hold fewer than 2^32 bytes.
+// Two-iteration configurations are refused for larger planes in both dtypes.
 inline bool plane32_ok(int esz, int ny, int nz)
 {
-    return esz == 8 || (long long)ny * pitch_of(esz, nz) * esz < (1LL << 32);
+    return (long long)ny * pitch_of(esz, nz) * esz < (1LL << 32);
 }
 
 // LDS bytes per staged plane of the flat kernel.
@@ -130,6 +130,12 @@ hipError_t launch_finalize(const double* part, long long stride, int n, const in
                            int nseg, int nslots, double* out, hipStream_t st);
 
 hipError_t launch_copy(void* dst, const void* src, unsigned long long bytes, hipStream_t st);
+
+// Fill coefficient q's block of a solve's side array (see side_index) from
+// the coefficient's field: coef addresses element (0,0,0), side the block.
+template <typename T>
+hipError_t launch_side_gather(const T* coef, T* side, int nx, int ny, int nz, long long P, long long S,
+                              hipStream_t st);
 
 // 13-read / 1-write streaming probe over the interior (bj 4, V = 1 or 4).
 template <typename T>

@@ -404,19 +404,26 @@ __device__ __forceinline__ T oload(const T* base, unsigned off)
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // Steps of prefetch of the two-iteration tiles (0: the synchronous tiles;
-// PD > 0: tile2_prefetch) for the FP32 single-solve kernels: two where a
+// PD > 0: tile2_prefetch) for the single-solve kernels. FP32: two where a
 // workgroup of `waves` waves (asking for at least min_waves waves per SIMD)
 // leaves each wave the 168 registers of three waves per SIMD, one where it
 // leaves 128 (the four register sets of two steps do not fit there). FP64
-// cannot hold the extra register sets and keeps the synchronous tile. The
-// batch kernels keep the synchronous tiles too: on batch64 the prefetching
-// one lost 9% (FP32, two steps) and the one-step form 9% (FP32) and 8%
-// (FP64); with small ragged grids more lanes load clamped addresses, and the
-// chunks' prologues and ends weigh more.
+// (wide: 64-cell rows only, which read their halo columns' coefficients
+// from the side array): one step where a wave has 168 registers, else the
+// synchronous tile; the 62- and 30-cell FP64 kernels keep the synchronous
+// tile. The batch kernels keep the synchronous tiles too: on batch64 the
+// prefetching one lost 9% (FP32, two steps) and the one-step form 9% (FP32)
+// and 8% (FP64); with small ragged grids more lanes load clamped addresses,
+// and the chunks' prologues and ends weigh more.
 template <typename T>
 constexpr int prefetch_single(int waves, int min_waves)
 {
     return sizeof(T) != 4 ? 0 : (waves <= 12 && min_waves <= 3) ? 2 : 1;
+}
+template <typename T>
+constexpr int prefetch_wide(int bj)
+{
+    return sizeof(T) == 4 ? prefetch_single<T>(bj + 3, 1) : (bj + 3 <= 12 ? 1 : 0);
 }
 
 // A thread's first-iteration cell in a two-iteration tile whose p0 tile
@@ -446,7 +453,7 @@ struct TileCell {
 // The p0 tile is fetched as a flat array (two cells per thread). Byte offsets
 // within a plane are 32-bit: a plane must hold fewer than 2^32 bytes
 // (plane32_ok).
-template <typename T, typename Lds, bool NT, bool KEEP, int PD>
+template <typename T, typename Lds, bool NT, bool KEEP, int PD, bool SIDE>
 __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0, int k0, const TileCell& tc, int ib,
                                                int ie, Lds& sm, double& acc1, double& acc2)
 {
@@ -487,10 +494,24 @@ __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0
         if (pcell[0] >= 0) f[pcell[0]] = x[0];
         if (pcell[1] >= 0) f[pcell[1]] = x[1];
     };
+    // SIDE (64-cell rows): the halo wave (the last one) reads its cells'
+    // coefficients from the side array, 2*(bj+2) consecutive elements per
+    // coefficient and plane, instead of one cache line per cell
+    const bool side_wave = SIDE && (int)(threadIdx.x / kWave) == Lds::NW - 1;
+    const long long side_q = (long long)g.nx * g.side_kt * 2 * g.ny, side_i = (long long)g.side_kt * 2 * g.ny;
+    const unsigned soff = (unsigned)((side_index(0, 0, (k0 - 1) / kWave, clampi(j, 0, g.ny - 1), threadIdx.x & 1, g.nx,
+                                                 g.ny, g.side_kt)) *
+                                     (long long)sizeof(T));
     auto coefs = [&](int ii, T (&x)[NCOEF]) {
-        const long long o = plane(ii);
+        if (side_wave) {
+            const T* b = g.side + (long long)clampi(ii, 0, g.nx - 1) * side_i;
 #pragma unroll
-        for (int q = 0; q < NCOEF; ++q) x[q] = oload<T, NT>(g.coef[q] + o, coff);
+            for (int q = 0; q < NCOEF; ++q) x[q] = oload<T, false>(b + q * side_q, soff);
+        } else {
+            const long long o = plane(ii);
+#pragma unroll
+            for (int q = 0; q < NCOEF; ++q) x[q] = oload<T, NT>(g.coef[q] + o, coff);
+        }
     };
 
     const int i_lo = ib - 1, i_hi = ie;                    // first-iteration planes
@@ -831,7 +852,7 @@ __device__ __forceinline__ void fused_block(const Grid<T>& g, T omega, int kt, i
         fused_tile<T, BJ, W, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
     } else {
         const int k0 = 1 + kt * FusedLds<T, BJ, W>::TK, j0 = 1 + jt * BJ;
-        tile2_prefetch<T, FusedLds<T, BJ, W>, NT, KEEP, PF>(
+        tile2_prefetch<T, FusedLds<T, BJ, W>, NT, KEEP, PF, false>(
             g, omega, j0, k0, fused_cell<BJ, W>(j0, k0), ib, ie, sm,
                                                            acc1, acc2);
     }
@@ -874,6 +895,7 @@ __global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fu
     g.src = d.f[parity];
     g.dst = d.f[parity ^ 1];
     g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.P = d.P; g.S = d.S;
+    g.side = nullptr; g.side_kt = 0;
     const int t = L - d.tile0;
     const int kt = t % d.kt_n;
     const int jt = (t / d.kt_n) % d.jt_n;
@@ -1123,7 +1145,7 @@ __device__ __forceinline__ void wide_block(const Grid<T>& g, T omega, int kt, in
         wide_tile_sync<T, BJ, NT, KEEP>(g, omega, kt, jt, ib, ie, sm, acc1, acc2);
     } else {
         const int k0 = 1 + kt * kWave, j0 = 1 + jt * BJ;
-        tile2_prefetch<T, WideLds<T, BJ>, NT, KEEP, PF>(g, omega, j0, k0, wide_cell<BJ>(j0, k0), ib, ie, sm, acc1,
+        tile2_prefetch<T, WideLds<T, BJ>, NT, KEEP, PF, true>(g, omega, j0, k0, wide_cell<BJ>(j0, k0), ib, ie, sm, acc1,
                                                        acc2);
     }
     acc1 = block_sum<BJ + 3>(acc1, sm.red);
@@ -1142,7 +1164,7 @@ __global__ __launch_bounds__(kWave * (BJ + 3)) void wide_kernel(Grid<T> g, T ome
     const int kt = L % kt_n;
     const int jt = (L / kt_n) % jt_n;
     const int ic = L / (kt_n * jt_n);
-    wide_block<T, BJ, NT, KEEP, prefetch_single<T>(BJ + 3, 1)>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
+    wide_block<T, BJ, NT, KEEP, prefetch_wide<T>(BJ)>(g, omega, kt, jt, ic, ichunk, L, sm, part1, part2);
 }
 
 template <typename T, int BJ, bool NT, bool KEEP>
@@ -1161,6 +1183,7 @@ __global__ __launch_bounds__(kWave * (BJ + 3)) void wide_batch_kernel(const Inst
     g.src = d.f[parity];
     g.dst = d.f[parity ^ 1];
     g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.P = d.P; g.S = d.S;
+    g.side = nullptr; g.side_kt = 0;
     const int t = L - d.tile0;
     const int kt = t % d.kt_n;
     const int jt = (t / d.kt_n) % d.jt_n;
@@ -1330,6 +1353,7 @@ __global__ __launch_bounds__(kWave * BJ) void batch_kernel(const Instance<T>* __
         g.src = d.f[parity];
         g.dst = d.f[parity ^ 1];
         g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.P = d.P; g.S = d.S;
+    g.side = nullptr; g.side_kt = 0;
         const int t = L - d.tile0;
         const int kt = t % d.kt_n;
         const int jt = (t / d.kt_n) % d.jt_n;
@@ -1361,6 +1385,7 @@ __global__ __launch_bounds__(kWave * NW) void flat_batch_kernel(const Instance<T
         g.src = d.f[parity];
         g.dst = d.f[parity ^ 1];
         g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.P = d.P; g.S = d.S;
+    g.side = nullptr; g.side_kt = 0;
         const int t = L - d.tile0;
         const int ct = t % d.kt_n;
         const int ic = t / d.kt_n;
@@ -1398,6 +1423,30 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double* __restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0) out[(long long)slot * nseg + seg] = red[0];
+}
+
+// ---- side array of the 64-cell-row tiles ------------------------------------------
+
+// side[side_index(q, i, kt, j, s)] = coefficient q at (i, j, 64 kt) for s = 0 and
+// at (i, j, min(64 kt + 65, nz - 1)) for s = 1, for one coefficient q (side
+// points at its block): a plain gather, run when the coefficient is uploaded.
+template <typename T>
+__global__ __launch_bounds__(256) void side_gather_kernel(const T* __restrict__ coef, T* __restrict__ side, int nx, int ny,
+                                                          int nz, long long P, long long S, int ktn)
+{
+    const long long n = (long long)nx * ktn * ny * 2;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+        long long r = t;
+        const int s = (int)(r % 2);
+        r /= 2;
+        const int j = (int)(r % ny);
+        r /= ny;
+        const int kt = (int)(r % ktn);
+        const int i = (int)(r / ktn);
+        int k = s ? kWave * kt + kWave + 1 : kWave * kt;
+        if (k > nz - 1) k = nz - 1;
+        side[t] = coef[(long long)i * S + (long long)j * P + k];
+    }
 }
 
 // ---- bandwidth probe and helpers ------------------------------------------------

@@ -203,6 +203,31 @@ def test_run_to_run_deterministic():
         assert np.array_equal(hist, outs[0][1])   # fixed-order reduction: same bits
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_coefficient_upload_between_sweeps(dtype):
+    """Coefficients uploaded between sweeps reach every cell the two-iteration
+    tiles read, the columns on the k tile edges included (the upload refreshes
+    the compact copy of those that the 64-cell-row kernel reads)."""
+    shape = (12, 19, 140)   # three 64-cell k tiles, the last one ragged
+    f, g = inputs.fields(2002, shape), inputs.fields(7, shape, bnd_mode=1)
+    with hj.Solver(dtype, shape) as s:
+        s.config = cfg(bj=8, vec=2, ichunk=5, nontemporal=0, xcd_remap=1, tsteps=2)
+        say("coefficient upload", dtype, shape, cfg_id(s.config))
+        s.upload_all(f)
+        s.sweep(2, 0.8)
+        for n in inputs.INPUTS[1:]:
+            s.upload(n, g[n])
+        s.sweep(4, 0.8)
+        p, hist = s.download("p"), s.gosa_history.copy()
+    p1, w1, _ = oracle.sweep(f, 2, 0.8)
+    pref, _, href = oracle.sweep(dict(g, p=p1, wrk2=w1), 4, 0.8)
+    if dtype == "f64":
+        assert np.array_equal(p, pref)
+        assert gosa_err(hist, href) <= F64_GOSA_RTOL
+    else:
+        assert field_err(p, pref) <= F32_FIELD_RTOL
+
+
 def test_download_coefficients_round_trip():
     shape = (6, 7, 9)
     f = inputs.fields(2002, shape)
