@@ -96,8 +96,8 @@ struct Layout {
     int nx = 0, ny = 0, nz = 0, esz = 0, A = 0;
     long long P = 0, S = 0;
     size_t field_bytes = 0, field_stride = 0, slab_bytes = 0;
-    // A single solve's slab also holds the side array of the 64-cell-row
-    // tiles (side_index) after its fields; a batch instance holds the fields only.
+    // A solve's slab (and each batch instance's part of a batch slab) also
+    // holds the side array of the 64-cell-row tiles (side_index) after its fields.
     size_t fields_bytes = 0, side_bytes = 0;
     int side_kt = 0;
 };
@@ -131,6 +131,20 @@ bool make_layout(int dtype, int nx, int ny, int nz, Layout& L)
     L.side_bytes = ((size_t)NCOEF * nx * L.side_kt * ny * 2 * L.esz + 255) / 256 * 256;
     L.slab_bytes = L.fields_bytes + L.side_bytes;
     return true;
+}
+
+// Refresh coefficient field's block of a side array (see side_index) from
+// the field at `origin` (its element (0,0,0)); waits for the gather.
+void gather_side(int dtype, const Layout& L, int field, const char* origin, char* side, hipStream_t st)
+{
+    const size_t blk = (size_t)L.nx * L.side_kt * L.ny * 2 * (field - HJ_A0);
+    if (dtype == HJ_F64)
+        HIPCHK(launch_side_gather<double>(reinterpret_cast<const double*>(origin),
+                                          reinterpret_cast<double*>(side) + blk, L.nx, L.ny, L.nz, L.P, L.S, st));
+    else
+        HIPCHK(launch_side_gather<float>(reinterpret_cast<const float*>(origin), reinterpret_cast<float*>(side) + blk,
+                                         L.nx, L.ny, L.nz, L.P, L.S, st));
+    HIPCHK(hipStreamSynchronize(st));
 }
 
 int check_dtype(int dtype)
@@ -1432,19 +1446,7 @@ int solver_upload(hj_solver h, int field, const void* src, bool src_f64)
             h->parity = 0;
         } else {
             copy_in(h->L, h->field(field), src, src_f64, h->stream);
-            // the coefficient's halo columns into the side array
-            const Layout& L = h->L;
-            const int q = field - HJ_A0;
-            const size_t blk = (size_t)L.nx * L.side_kt * L.ny * 2;
-            if (h->dtype == HJ_F64)
-                HIPCHK(launch_side_gather<double>(reinterpret_cast<const double*>(h->origin(field)),
-                                                  reinterpret_cast<double*>(h->side()) + q * blk, L.nx, L.ny,
-                                                  L.nz, L.P, L.S, h->stream));
-            else
-                HIPCHK(launch_side_gather<float>(reinterpret_cast<const float*>(h->origin(field)),
-                                                 reinterpret_cast<float*>(h->side()) + q * blk, L.nx, L.ny, L.nz,
-                                                 L.P, L.S, h->stream));
-            HIPCHK(hipStreamSynchronize(h->stream));
+            gather_side(h->dtype, h->L, field, h->origin(field), h->side(), h->stream);
         }
         h->uploaded |= 1u << field;
         return HJ_OK;
@@ -1929,6 +1931,7 @@ struct hj_batch_s {
 
     char* field(int inst, int q) const { return slab + off[inst] + (size_t)q * L[inst].field_stride; }
     char* origin(int inst, int q) const { return field(inst, q) + (size_t)(L[inst].A - 1) * L[inst].esz; }
+    char* side(int inst) const { return slab + off[inst] + L[inst].fields_bytes; }
 
     bool two() const { return fused_of(cfg); }
     hj_config single_cfg() const
@@ -1954,6 +1957,8 @@ struct hj_batch_s {
             d.f[1] = reinterpret_cast<T*>(origin(t, HJ_WRK2));
             for (int q = 0; q < NCOEF; ++q) d.coef[q] = reinterpret_cast<const T*>(origin(t, HJ_A0 + q));
             d.nx = l.nx; d.ny = l.ny; d.nz = l.nz; d.P = l.P; d.S = l.S;
+            d.side = reinterpret_cast<const T*>(side(t));
+            d.side_kt = l.side_kt;
             const TileCounts tc = tile_counts(c, l.nx, l.ny, l.nz);
             d.kt_n = tc.kt_n;
             d.jt_n = tc.jt_n;
@@ -2161,7 +2166,7 @@ int hj_batch_create(hj_batch* out, int dtype, int n, const int* nx, const int* n
                 return set_err(HJ_ERR_SHAPE, "instance %d: invalid shape %dx%dx%d", t, nx[t], ny[t], nz[t]);
             }
             b->off[t] = total;
-            total += b->L[t].fields_bytes;
+            total += b->L[t].slab_bytes;
         }
         b->slab_bytes = total;
         b->cfg = batch_default(dtype);
@@ -2223,6 +2228,7 @@ int batch_upload(hj_batch b, int inst, int field, const void* src, bool src_f64)
             copy_in(b->L[inst], b->field(inst, HJ_WRK2), src, src_f64, b->stream);
         } else {
             copy_in(b->L[inst], b->field(inst, field), src, src_f64, b->stream);
+            gather_side(b->dtype, b->L[inst], field, b->origin(inst, field), b->side(inst), b->stream);
         }
         b->uploaded[inst] |= 1u << field;
         return HJ_OK;

@@ -1183,12 +1183,12 @@ __global__ __launch_bounds__(kWave * (BJ + 3)) void wide_batch_kernel(const Inst
     g.src = d.f[parity];
     g.dst = d.f[parity ^ 1];
     g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.P = d.P; g.S = d.S;
-    g.side = nullptr; g.side_kt = 0;
+    g.side = d.side; g.side_kt = d.side_kt;
     const int t = L - d.tile0;
     const int kt = t % d.kt_n;
     const int jt = (t / d.kt_n) % d.jt_n;
     const int ic = t / (d.kt_n * d.jt_n);
-    wide_block<T, BJ, NT, KEEP, 0>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
+    wide_block<T, BJ, NT, KEEP, prefetch_wide<T>(BJ)>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
 }
 
 // ---- flat kernel: tiles of consecutive interior (j,k) cells -------------------

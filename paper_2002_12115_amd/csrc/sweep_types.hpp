@@ -45,6 +45,8 @@ struct Instance {
     long long P, S;
     int kt_n, jt_n, ichunk;
     int tile0;          // first tile of this instance in the flattened list
+    const T* side;      // the instance's side array (as Grid::side)
+    int side_kt;
 };
 
 // Number of i chunks of length ichunk over the interior.
