@@ -2,6 +2,7 @@
 #include "hj_launch.hpp"
 #include "sweep_kernels.hpp"
 
+#include <atomic>
 #include <type_traits>
 
 namespace hj {
@@ -19,7 +20,7 @@ hipError_t march_go(const hj_config& c, const Grid<T>& g, T omega, double* part,
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((march_kernel<T, BJ, V, NT, W>), dim3((unsigned)nb), dim3(kWave * BJ), 0, st,
-                       g, omega, c.ichunk, t.kt_n, t.jt_n, c.xcd_remap, part);
+                       g, omega, c.ichunk, t.kt_n, t.jt_n, c.xcd_remap ? (int)nb : 0, part);
     return hipGetLastError();
 }
 
@@ -31,7 +32,7 @@ hipError_t direct_go(const hj_config& c, const Grid<T>& g, T omega, double* part
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((direct_kernel<T, BJ, NT, W>), dim3((unsigned)nb), dim3(kWave * BJ), 0, st,
-                       g, omega, t.kt_n, t.jt_n, c.xcd_remap, part);
+                       g, omega, t.kt_n, t.jt_n, c.xcd_remap ? (int)nb : 0, part);
     return hipGetLastError();
 }
 
@@ -151,7 +152,7 @@ hipError_t flat_go(const hj_config& c, const Grid<T>& g, T omega, double* part, 
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((flat_kernel<T, NW, NT, W>), dim3((unsigned)nb), dim3(kWave * NW), 0, st, g, omega,
-                       c.ichunk, t.kt_n, c.xcd_remap, part);
+                       c.ichunk, t.kt_n, c.xcd_remap ? (int)nb : 0, part);
     return hipGetLastError();
 }
 
@@ -251,6 +252,29 @@ int batch_occupancy(const hj_config& c)
 
 namespace {
 
+// The remap window of a single-grid two-iteration launch (see remap_xcd):
+// the workgroups of `kernel` resident on the current device at once, a
+// multiple of 8; 0 without the remap. Queried once per kernel and device:
+// `cache` is the kernel's own table (one entry per device, 0 until queried).
+constexpr int kMaxDevices = 64;
+template <typename K>
+int remap_window(const hj_config& c, K kernel, int threads, std::atomic<int>* cache)
+{
+    if (!c.xcd_remap) return 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = 0;
+    int w = cache[dev].load(std::memory_order_relaxed);
+    if (w == 0) {
+        int occ = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) != hipSuccess) occ = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+        w = occ * cus / 8 * 8;
+        if (w <= 0) w = 0x7fffffff;  // no answer: deal the whole grid, as with one window
+        cache[dev].store(w, std::memory_order_relaxed);
+    }
+    return w;
+}
+
 template <typename T, int BJ, int W, bool NT, bool KEEP>
 hipError_t fused_go(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                     hipStream_t st)
@@ -260,9 +284,10 @@ hipError_t fused_go(const hj_config& c, const Grid<T>& g, T omega, double* part1
     const long long nb = t.tiles();
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    static std::atomic<int> wcache[kMaxDevices];
+    const int win = remap_window(c, fused_kernel<T, BJ, W, NT, KEEP>, fused_threads<BJ, W>(), wcache);
     hipLaunchKernelGGL((fused_kernel<T, BJ, W, NT, KEEP>), dim3((unsigned)nb), dim3(fused_threads<BJ, W>()), 0, st,
-                       g, omega,
-                       c.ichunk, t.kt_n, t.jt_n, c.xcd_remap, part1, part2);
+                       g, omega, c.ichunk, t.kt_n, t.jt_n, win, part1, part2);
     return hipGetLastError();
 }
 
@@ -271,8 +296,10 @@ hipError_t fused_batch_go(const hj_config& c, const Instance<T>* inst, const int
                           int parity, T omega, double* part1, double* part2, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
+    // a batch deals its whole tile list in eighths: each XCD keeps whole instances in its L2
+    const int win = c.xcd_remap ? ntiles : 0;
     hipLaunchKernelGGL((fused_batch_kernel<T, BJ, W, NT, KEEP>), dim3((unsigned)ntiles),
-                       dim3(fused_threads<BJ, W>()), 0, st, inst, tile_inst, parity, omega, c.xcd_remap, part1, part2);
+                       dim3(fused_threads<BJ, W>()), 0, st, inst, tile_inst, parity, omega, win, part1, part2);
     return hipGetLastError();
 }
 
@@ -286,8 +313,10 @@ hipError_t wide_go(const hj_config& c, const Grid<T>& g, T omega, double* part1,
     const long long nb = t.tiles();
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    static std::atomic<int> wcache[kMaxDevices];
+    const int win = remap_window(c, wide_kernel<T, BJ, NT, KEEP>, kWave * (BJ + 3), wcache);
     hipLaunchKernelGGL((wide_kernel<T, BJ, NT, KEEP>), dim3((unsigned)nb), dim3(kWave * (BJ + 3)), 0, st, g, omega,
-                       c.ichunk, t.kt_n, t.jt_n, c.xcd_remap, part1, part2);
+                       c.ichunk, t.kt_n, t.jt_n, win, part1, part2);
     return hipGetLastError();
 }
 
@@ -296,8 +325,9 @@ hipError_t wide_batch_go(const hj_config& c, const Instance<T>* inst, const int*
                          int parity, T omega, double* part1, double* part2, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
+    const int win = c.xcd_remap ? ntiles : 0;  // as for fused_batch_go
     hipLaunchKernelGGL((wide_batch_kernel<T, BJ, NT, KEEP>), dim3((unsigned)ntiles), dim3(kWave * (BJ + 3)), 0,
-                       st, inst, tile_inst, parity, omega, c.xcd_remap, part1, part2);
+                       st, inst, tile_inst, parity, omega, win, part1, part2);
     return hipGetLastError();
 }
 

@@ -134,12 +134,18 @@ __device__ __forceinline__ double block_sum(double v, double* red)
 
 // Workgroup number -> logical tile number. Workgroups are dealt round-robin
 // to the 8 XCDs; with the remap, logical neighbours (adjacent k/j tiles, which
-// share halo rows) run on the same XCD and so share its L2.
-__device__ __forceinline__ int remap_xcd(int b, int nb, int on)
+// share halo rows) run on the same XCD and so share its L2. The remap works
+// within windows of `win` consecutive workgroups (a multiple of 8; 0: no
+// remap): with win = the workgroups resident at once, the tiles in flight at
+// any time stay one compact block of the grid, each XCD holding a contiguous
+// eighth of it; with win >= nb the whole grid is dealt in eighths.
+__device__ __forceinline__ int remap_xcd(int b, int nb, int win)
 {
-    if (!on) return b;
-    const int q = nb >> 3, r = nb & 7, x = b & 7;
-    return x * q + (x < r ? x : r) + (b >> 3);
+    if (win <= 0) return b;
+    const int base = win < nb ? b / win * win : 0;
+    const int n = win < nb - base ? win : nb - base, u = b - base;
+    const int q = n >> 3, r = n & 7, x = u & 7;
+    return base + x * q + (x < r ? x : r) + (u >> 3);
 }
 
 // ---- march kernel: (j,k) tile per workgroup, LDS ring of p planes, march in i
