@@ -524,15 +524,19 @@ __device__ __forceinline__ void tile2_prefetch(const Grid<T>& g, T omega, int j0
     static_assert(PD == 1 || PD == 2, "prefetch distance");
     constexpr int NS = PD + 2;                             // register sets
     T ps[NS][2], cs[NS][NCOEF];
-    for (int ii = i_lo - 1; ii <= i_lo + 1; ++ii) {
-        fetch(ii, ps[0]);
-        put(ii, ps[0]);
-    }
+    // prologue: the first three p0 planes and the first PD steps' loads are
+    // all issued before the first LDS store waits, so the chunk start costs
+    // one memory latency rather than one per plane
+    T pro[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fetch(i_lo - 1 + d, pro[d]);
 #pragma unroll
     for (int d = 0; d < PD; ++d) {
         fetch(min(i_lo + 2 + d, i_hi + 1), ps[d]);
         coefs(min(i_lo + d, i_hi), cs[d]);
     }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) put(i_lo - 1 + d, pro[d]);
     // the first step's second iteration (plane i_lo-1) has no output: its set
     // only needs defined values
 #pragma unroll
@@ -735,10 +739,15 @@ __device__ __forceinline__ void fused_tile(const Grid<T>& g, T omega, int kt, in
     // p0 planes ib-2 .. ib (clipped at the shell)
     const int i_lo = ib - 1, i_hi = ie;                          // first-iteration planes
     P0Regs<T> rr;
-    for (int ii = i_lo - 1; ii <= i_lo + 1; ++ii) {
-        if (ii < 0) continue;
-        fused_fetch<T, BJ, W>(g, ii, j0, k0, rr);
-        fused_put<T, BJ, W>(g, sm.p0[ii & 3], j0, k0, rr);
+    {
+        // the first three planes' loads all issued before the first LDS store
+        P0Regs<T> pro[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (i_lo - 1 + d >= 0) fused_fetch<T, BJ, W>(g, i_lo - 1 + d, j0, k0, pro[d]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (i_lo - 1 + d >= 0) fused_put<T, BJ, W>(g, sm.p0[(i_lo - 1 + d) & 3], j0, k0, pro[d]);
     }
     __syncthreads();
 
@@ -1018,10 +1027,15 @@ __device__ __forceinline__ void wide_tile_sync(const Grid<T>& g, T omega, int kt
 
     const int i_lo = ib - 1, i_hi = ie;                    // first-iteration planes
     WideRegs<T> rr;
-    for (int ii = i_lo - 1; ii <= i_lo + 1; ++ii) {
-        if (ii < 0) continue;
-        wide_fetch<T, BJ>(g, ii, j0, k0, rr);
-        wide_put<T, BJ>(g, sm.p0[ii & 3], j0, k0, rr);
+    {
+        // the first three planes' loads all issued before the first LDS store
+        WideRegs<T> pro[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (i_lo - 1 + d >= 0) wide_fetch<T, BJ>(g, i_lo - 1 + d, j0, k0, pro[d]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (i_lo - 1 + d >= 0) wide_put<T, BJ>(g, sm.p0[(i_lo - 1 + d) & 3], j0, k0, pro[d]);
     }
     __syncthreads();
 
