@@ -203,6 +203,28 @@ def test_run_to_run_deterministic():
         assert np.array_equal(hist, outs[0][1])   # fixed-order reduction: same bits
 
 
+@pytest.mark.parametrize("dtype,c", [
+    ("f64", dict(bj=4, vec=2, ichunk=1)), ("f64", dict(bj=8, vec=1, ichunk=2)),
+    ("f32", dict(bj=8, vec=2, ichunk=1)), ("f32", dict(bj=14, vec=4, ichunk=3))],
+    ids=["f64-wide", "f64-fused", "f32-wide", "f32-narrow"])
+def test_remap_windows_with_a_partial_last_window(dtype, c):
+    """Single-grid two-iteration launches deal tiles to XCDs in windows of
+    the workgroups resident at once; a grid of several windows and a
+    partial last one (thousands of tiles, not a multiple of the window)
+    still computes every tile exactly once."""
+    shape = (41, 131, 133)          # 39 planes in chunks of 1-3; ragged j and k tiles
+    n = 4
+    conf = cfg(nontemporal=0, xcd_remap=1, tsteps=2, reread=0, **c)
+    say("remap windows", dtype, shape, cfg_id(conf))
+    p, hist, _ = gpu_run(shape, dtype, n, cfg=conf)
+    pref, href = oracle_cached(shape, n)
+    if dtype == "f64":
+        assert np.array_equal(p, pref)
+        assert gosa_err(hist, href) <= F64_GOSA_RTOL
+    else:
+        assert field_err(p, pref) <= F32_FIELD_RTOL
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_coefficient_upload_between_sweeps(dtype):
     """Coefficients uploaded between sweeps reach every cell the two-iteration
