@@ -903,6 +903,12 @@ struct hj_solver_s {
         return c;
     }
     long long tiles_of(const hj_config& c) const { return tile_counts(c, L.nx, L.ny, L.nz).tiles(); }
+    // the runtime queries of cfg's launches, made now (outside any capture)
+    void prime() const
+    {
+        if (dtype == HJ_F64) prime_remap<double>(cfg);
+        else prime_remap<float>(cfg);
+    }
     // Partials per iteration slot (room for either kernel's tiles).
     long long stride() const { return std::max(tiles_of(cfg), tiles_of(single_cfg())); }
     long long tiles() const { return tiles_of(cfg); }
@@ -1374,6 +1380,7 @@ void apply_start_config(hj_solver h)
         c.persistent = 0;
         h->cfg = c;
     }
+    h->prime();
 }
 
 }  // namespace
@@ -1624,6 +1631,7 @@ int hj_set_config(hj_solver h, const hj_config* cfg)
         h->cfg.persistent = 0;
         if (h->cfg.tsteps == 0) h->cfg.tsteps = 1;
         if (h->cfg.tsteps == 1) h->cfg.reread = 0;
+        h->prime();
         return HJ_OK;
     });
 }
@@ -1706,6 +1714,7 @@ struct SolverTuning {
         }
         h->cfg = win;
         h->cfg.use_graph = keep.use_graph;
+        h->prime();
         cache_put("solve", h->dtype, solve_key(h->L.nx, h->L.ny, h->L.nz), h->cfg, win_ms);
         if (best) *best = h->cfg;
         if (best_ms) *best_ms = win_ms;

@@ -275,6 +275,21 @@ int remap_window(const hj_config& c, K kernel, int threads, std::atomic<int>* ca
     return w;
 }
 
+// Each two-iteration single-grid kernel's table of remap windows (one entry
+// per device), shared by its launcher and prime_remap.
+template <typename T, int BJ, int W, bool NT, bool KEEP>
+std::atomic<int>* fused_win()
+{
+    static std::atomic<int> c[kMaxDevices];
+    return c;
+}
+template <typename T, int BJ, bool NT, bool KEEP>
+std::atomic<int>* wide_win()
+{
+    static std::atomic<int> c[kMaxDevices];
+    return c;
+}
+
 template <typename T, int BJ, int W, bool NT, bool KEEP>
 hipError_t fused_go(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,
                     hipStream_t st)
@@ -284,8 +299,8 @@ hipError_t fused_go(const hj_config& c, const Grid<T>& g, T omega, double* part1
     const long long nb = t.tiles();
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    static std::atomic<int> wcache[kMaxDevices];
-    const int win = remap_window(c, fused_kernel<T, BJ, W, NT, KEEP>, fused_threads<BJ, W>(), wcache);
+    const int win =
+        remap_window(c, fused_kernel<T, BJ, W, NT, KEEP>, fused_threads<BJ, W>(), fused_win<T, BJ, W, NT, KEEP>());
     hipLaunchKernelGGL((fused_kernel<T, BJ, W, NT, KEEP>), dim3((unsigned)nb), dim3(fused_threads<BJ, W>()), 0, st,
                        g, omega, c.ichunk, t.kt_n, t.jt_n, win, part1, part2);
     return hipGetLastError();
@@ -313,8 +328,7 @@ hipError_t wide_go(const hj_config& c, const Grid<T>& g, T omega, double* part1,
     const long long nb = t.tiles();
     if (nb <= 0) return hipSuccess;
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
-    static std::atomic<int> wcache[kMaxDevices];
-    const int win = remap_window(c, wide_kernel<T, BJ, NT, KEEP>, kWave * (BJ + 3), wcache);
+    const int win = remap_window(c, wide_kernel<T, BJ, NT, KEEP>, kWave * (BJ + 3), wide_win<T, BJ, NT, KEEP>());
     hipLaunchKernelGGL((wide_kernel<T, BJ, NT, KEEP>), dim3((unsigned)nb), dim3(kWave * (BJ + 3)), 0, st, g, omega,
                        c.ichunk, t.kt_n, t.jt_n, win, part1, part2);
     return hipGetLastError();
@@ -423,6 +437,51 @@ int fused_occupancy(const hj_config& c)
 
 template int fused_occupancy<double>(const hj_config&);
 template int fused_occupancy<float>(const hj_config&);
+
+namespace {
+
+template <typename T, int BJ>
+void prime_bj(const hj_config& c)
+{
+    with_modes(c, [&](auto nt, auto keep) -> int {
+        constexpr bool NT = decltype(nt)::value, KEEP = decltype(keep)::value;
+        if (c.vec == 1) {
+            if constexpr (fused_bj_ok(1, BJ))
+                (void)remap_window(c, fused_kernel<T, BJ, kWave, NT, KEEP>, fused_threads<BJ, kWave>(),
+                                   fused_win<T, BJ, kWave, NT, KEEP>());
+        } else if (c.vec == 2) {
+            if constexpr (fused_bj_ok(2, BJ))
+                (void)remap_window(c, wide_kernel<T, BJ, NT, KEEP>, kWave * (BJ + 3), wide_win<T, BJ, NT, KEEP>());
+        } else if (c.vec == 4) {
+            if constexpr (fused_bj_ok(4, BJ))
+                (void)remap_window(c, fused_kernel<T, BJ, kWave / 2, NT, KEEP>, fused_threads<BJ, kWave / 2>(),
+                                   fused_win<T, BJ, kWave / 2, NT, KEEP>());
+        }
+        return 0;
+    });
+}
+
+}  // namespace
+
+template <typename T>
+void prime_remap(const hj_config& c)
+{
+    if (c.tsteps != 2 || !c.xcd_remap || !fused_bj_ok(c.vec, c.bj)) return;
+    switch (c.bj) {
+    case 2: prime_bj<T, 2>(c); break;
+    case 4: prime_bj<T, 4>(c); break;
+    case 6: prime_bj<T, 6>(c); break;
+    case 8: prime_bj<T, 8>(c); break;
+    case 12: prime_bj<T, 12>(c); break;
+    case 14: prime_bj<T, 14>(c); break;
+    case 22: prime_bj<T, 22>(c); break;
+    case 30: prime_bj<T, 30>(c); break;
+    default: break;
+    }
+}
+
+template void prime_remap<double>(const hj_config&);
+template void prime_remap<float>(const hj_config&);
 
 template <typename T>
 hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* part1, double* part2,

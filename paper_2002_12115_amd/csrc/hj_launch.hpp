@@ -111,6 +111,13 @@ template <typename T>
 hipError_t launch_batch_fused(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
                               int parity, T omega, double* part1, double* part2, hipStream_t st);
 
+// Query, outside any stream capture, what the launch of c's single-grid
+// two-iteration kernel on the current device will ask the runtime (its XCD
+// remap window), so that later launches, captured ones included, make no
+// runtime query. Does nothing for other configurations.
+template <typename T>
+void prime_remap(const hj_config& c);
+
 // Workgroups of the two-iteration kernel named by c resident per CU (0 when
 // c names none, or the query fails).
 template <typename T>

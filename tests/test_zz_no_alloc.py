@@ -146,3 +146,53 @@ def test_noalloc_captured_in_a_graph_and_replayed(lib):
             assert gosa_err(dev.cpu().numpy(), href[(r - 1) * n:r * n]) <= F64_GOSA_RTOL, r
     finally:
         _ok(lib, lib.hj_destroy(h), "hj_destroy")
+
+
+FRESH_CAPTURE = r"""
+import ctypes, sys
+import numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+sys.path.insert(0, sys.argv[1] + "/tests")
+import oracle
+from paper_2002_12115_amd import hj, inputs
+lib = hj.load()
+shape, n, omega = (34, 36, 70), 4, 0.8
+f = inputs.fields(5, shape)
+stream = torch.cuda.Stream()
+h = ctypes.c_void_p()
+assert lib.hj_create(ctypes.byref(h), hj.F64, *shape, ctypes.c_void_p(stream.cuda_stream)) == 0
+for name in inputs.INPUTS:
+    a = np.ascontiguousarray(f[name], dtype=np.float64)
+    assert lib.hj_upload_f64(h, inputs.FIELD_ID[name], a.ctypes.data) == 0
+c = hj.Config.make(kernel=1, bj=8, vec=2, ichunk=7, nontemporal=0, use_graph=1, xcd_remap=1, persistent=0,
+                   tsteps=2, reread=0)
+assert lib.hj_set_config(h, ctypes.byref(c)) == 0
+dev = torch.zeros(n, dtype=torch.float64, device="cuda")
+torch.cuda.synchronize()
+g = torch.cuda.CUDAGraph()
+with torch.cuda.graph(g, stream=stream):      # the first launch of this kernel in the process
+    assert lib.hj_sweep_noalloc(h, n, ctypes.c_double(omega), ctypes.c_void_p(dev.data_ptr())) == 0
+g.replay()
+torch.cuda.synchronize()
+out = np.empty(shape, dtype=np.float64)
+assert lib.hj_download(h, inputs.FIELD_ID["p"], out.ctypes.data) == 0
+assert lib.hj_destroy(h) == 0
+pref = oracle.sweep(f, n, omega, nthreads=4)[0]
+assert np.array_equal(out, pref)
+print("fresh capture ok", flush=True)
+"""
+
+
+def test_noalloc_first_launch_inside_a_capture_in_a_fresh_process():
+    """In a new process, the first launch of a two-iteration kernel with the
+    XCD remap happens inside a caller's graph capture: the configuration call
+    made the runtime queries beforehand, so the capture holds, and one replay
+    gives the oracle's field bitwise."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    say("fresh-process capture of hj_sweep_noalloc")
+    r = subprocess.run([sys.executable, "-c", FRESH_CAPTURE, root], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "fresh capture ok" in r.stdout
