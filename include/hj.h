@@ -73,7 +73,10 @@ enum hj_field {
  * march kernel (>= 1; splits the march so the grid fills the chip).
  * nontemporal: stream the 12 single-use arrays with non-temporal loads and
  * stores. use_graph: replay the sweep loop as a captured HIP graph.
- * xcd_remap: renumber workgroups so neighbouring tiles share an XCD's L2.
+ * xcd_remap: renumber workgroups so neighbouring tiles share an XCD's L2
+ * (two-iteration single solves: within windows of the workgroups resident
+ * at once, queried when the configuration is installed; one-iteration
+ * kernels and batches: over the whole grid or tile list).
  * persistent (batches only): launch as many workgroups as stay resident and
  * let each loop over tiles, instead of one workgroup per tile.
  * tsteps: Jacobi iterations per pass over memory. 1, or 2: the march
