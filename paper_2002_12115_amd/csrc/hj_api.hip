@@ -1980,14 +1980,38 @@ struct hj_batch_s {
         }
         seg[n] = (int)tile_inst.size();
         out.ntiles = (int)tile_inst.size();
+        if (fused_of(c)) {
+            // two-iteration lists: (instance, tile within it) pairs. Without
+            // XCD renumbering the tiles with the most planes go first
+            // (stable), so that the short remainder chunks fill the launch's
+            // last round; with it the list stays instance-major, so that each
+            // XCD's eighth of the list holds whole instances.
+            std::vector<int> order(out.ntiles);
+            std::vector<int> planes(out.ntiles);
+            for (int i = 0; i < out.ntiles; ++i) {
+                const Instance<T>& d = inst[tile_inst[i]];
+                const int t = i - d.tile0, ic = t / (d.kt_n * d.jt_n), ib = 1 + ic * d.ichunk;
+                planes[i] = std::min(ib + d.ichunk, d.nx - 1) - ib;
+                order[i] = i;
+            }
+            if (!c.xcd_remap)
+                std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return planes[a] > planes[b]; });
+            std::vector<int> pairs(2 * (size_t)out.ntiles);
+            for (int i = 0; i < out.ntiles; ++i) {
+                const int at = order[i], ti = tile_inst[at];
+                pairs[2 * (size_t)i] = ti;
+                pairs[2 * (size_t)i + 1] = at - inst[ti].tile0;
+            }
+            tile_inst.swap(pairs);
+        }
         out.d_inst.ensure(sizeof(Instance<T>) * std::max(n, 1));
-        out.d_tile_inst.ensure(sizeof(int) * std::max(out.ntiles, 1));
+        out.d_tile_inst.ensure(sizeof(int) * std::max(tile_inst.size(), (size_t)1));
         out.d_seg.ensure(sizeof(int) * (n + 1));
         // on the batch's own stream (a copy on the legacy stream would disturb
         // graph captures running on other threads)
         HIPCHK(hipMemcpyAsync(out.d_inst.p, inst.data(), sizeof(Instance<T>) * n, hipMemcpyHostToDevice, stream));
-        HIPCHK(hipMemcpyAsync(out.d_tile_inst.p, tile_inst.data(), sizeof(int) * out.ntiles, hipMemcpyHostToDevice,
-                              stream));
+        HIPCHK(hipMemcpyAsync(out.d_tile_inst.p, tile_inst.data(), sizeof(int) * tile_inst.size(),
+                              hipMemcpyHostToDevice, stream));
         HIPCHK(hipMemcpyAsync(out.d_seg.p, seg.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, stream));
         HIPCHK(hipStreamSynchronize(stream));
         if (c.persistent) {

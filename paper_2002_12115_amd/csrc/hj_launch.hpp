@@ -106,7 +106,9 @@ hipError_t launch_fused(const hj_config& c, const Grid<T>& g, T omega, double* p
 
 // Two iterations over every instance of a batch (tsteps 2, not persistent):
 // one workgroup per tile of the flattened list, built with the two-iteration
-// tile counts; per-tile partials of the two iterations to part1 and part2.
+// tile counts; tile_inst holds 2*ntiles ints, (instance, tile within the
+// instance) in dispatch order; per-tile partials of the two iterations to
+// part1 and part2 at the tiles' instance-major places.
 template <typename T>
 hipError_t launch_batch_fused(const hj_config& c, const Instance<T>* inst, const int* tile_inst, int ntiles,
                               int parity, T omega, double* part1, double* part2, hipStream_t st);

@@ -895,7 +895,10 @@ __global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fu
 
 // Two iterations over every instance of a batch: one workgroup per tile of
 // the flattened list (instance descriptors as for batch_kernel, with the
-// two-iteration tile counts), gridDim.x == the number of tiles.
+// two-iteration tile counts), gridDim.x == the number of tiles. tile_inst
+// holds, in dispatch order, (instance, tile within the instance) pairs; a
+// tile's gosa partials go to the slot of its place in the instance-major
+// list (tile0 + tile), which the per-instance reduction reads in order.
 template <typename T, int BJ, int W, bool NT, bool KEEP>
 __global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fused_min_waves<BJ, W>()))) void fused_batch_kernel(
     const Instance<T>* __restrict__ inst, const int* __restrict__ tile_inst, int parity, T omega, int remap,
@@ -903,7 +906,8 @@ __global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fu
 {
     __shared__ FusedLds<T, BJ, W> sm;
     const int L = remap_xcd(blockIdx.x, gridDim.x, remap);
-    const Instance<T>& d = inst[tile_inst[L]];
+    const Instance<T>& d = inst[tile_inst[2 * L]];
+    const int t = tile_inst[2 * L + 1];
     Grid<T> g;
 #pragma unroll
     for (int q = 0; q < NCOEF; ++q) g.coef[q] = d.coef[q];
@@ -911,11 +915,10 @@ __global__ __launch_bounds__((BJ + 2) * W) __attribute__((amdgpu_waves_per_eu(fu
     g.dst = d.f[parity ^ 1];
     g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.P = d.P; g.S = d.S;
     g.side = nullptr; g.side_kt = 0;
-    const int t = L - d.tile0;
     const int kt = t % d.kt_n;
     const int jt = (t / d.kt_n) % d.jt_n;
     const int ic = t / (d.kt_n * d.jt_n);
-    fused_block<T, BJ, W, NT, KEEP, 0>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
+    fused_block<T, BJ, W, NT, KEEP, 0>(g, omega, kt, jt, ic, d.ichunk, d.tile0 + t, sm, part1, part2);
 }
 
 // ---- wide fused kernel: 64 own cells per row and a halo wave -----------------
@@ -1196,7 +1199,8 @@ __global__ __launch_bounds__(kWave * (BJ + 3)) void wide_batch_kernel(const Inst
 {
     __shared__ WideLds<T, BJ> sm;
     const int L = remap_xcd(blockIdx.x, gridDim.x, remap);
-    const Instance<T>& d = inst[tile_inst[L]];
+    const Instance<T>& d = inst[tile_inst[2 * L]];     // as for fused_batch_kernel
+    const int t = tile_inst[2 * L + 1];
     Grid<T> g;
 #pragma unroll
     for (int q = 0; q < NCOEF; ++q) g.coef[q] = d.coef[q];
@@ -1204,11 +1208,11 @@ __global__ __launch_bounds__(kWave * (BJ + 3)) void wide_batch_kernel(const Inst
     g.dst = d.f[parity ^ 1];
     g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.P = d.P; g.S = d.S;
     g.side = d.side; g.side_kt = d.side_kt;
-    const int t = L - d.tile0;
     const int kt = t % d.kt_n;
     const int jt = (t / d.kt_n) % d.jt_n;
     const int ic = t / (d.kt_n * d.jt_n);
-    wide_block<T, BJ, NT, KEEP, prefetch_wide<T>(BJ)>(g, omega, kt, jt, ic, d.ichunk, L, sm, part1, part2);
+    wide_block<T, BJ, NT, KEEP, prefetch_wide<T>(BJ)>(g, omega, kt, jt, ic, d.ichunk, d.tile0 + t, sm, part1,
+                                                       part2);
 }
 
 // ---- flat kernel: tiles of consecutive interior (j,k) cells -------------------
