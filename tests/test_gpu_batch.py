@@ -90,6 +90,31 @@ def test_batch_equals_single_solves_bitwise():
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_dispatch_order_leaves_results_bitwise_unchanged(dtype):
+    """A two-iteration batch dispatches its tiles longest-first without XCD
+    renumbering and instance by instance with it; each tile's gosa partials
+    go to its instance-major place, so fields and gosa histories are bitwise
+    the same in both orders (and over chunk lengths that leave remainders)."""
+    shapes, seeds = inputs.batch_shapes(11, 9, lo_xy=5, hi_xy=70, lo_z=10, hi_z=140)
+    arrays = [inputs.fields(sd, sh) for sh, sd in zip(shapes, seeds)]
+    outs = []
+    for rm in (1, 0):
+        c = hj.Config.make(kernel=1, bj=6, vec=4 if dtype == "f64" else 2, ichunk=9, nontemporal=0, use_graph=1,
+                           xcd_remap=rm, persistent=0, tsteps=2, reread=0)
+        say("dispatch order", dtype, "xcd_remap", rm)
+        with hj.Batch(dtype, shapes) as b:
+            b.config = c
+            for t, a in enumerate(arrays):
+                b.upload_all(t, a)
+            b.sweep(8, 0.8)
+            outs.append(([b.download(t) for t in range(len(shapes))], b.gosa_history.copy()))
+    (p1, h1), (p0, h0) = outs
+    for t in range(len(shapes)):
+        assert np.array_equal(p1[t], p0[t]), t
+    assert np.array_equal(h1, h0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_two_iteration_batch_odd_counts_and_residual(dtype):
     """Odd iteration counts end on a one-iteration pass; the residual and the
     gosa history continue across calls, as for single solves."""
