@@ -135,7 +135,9 @@ def roofline(esz: int, n_int: int, tsteps: int, avg_launch_ms: float, traffic):
     bound on the real traffic, so frac never exceeds what HBM moved.
     measured: rocprofv3 FETCH_SIZE + WRITE_SIZE bytes per launch (calibrated
     against a copy of known size) / the same time, when the counters were
-    taken on the current kernel code and configuration (else null).
+    taken on the current kernel code and configuration (else null). These
+    count every byte that leaves the L2s; the memory-side cache may answer
+    part of the reads, so they bound the HBM bytes from above.
     per_update_equiv: the bytes a one-iteration kernel would move for the
     same updates, per second (a speed figure, not a fraction of HBM)."""
     s = avg_launch_ms * 1e-3
@@ -149,6 +151,8 @@ def roofline(esz: int, n_int: int, tsteps: int, avg_launch_ms: float, traffic):
            "measured_gbps": None, "measured_frac": None, "traffic_over_algorithmic": None,
            "per_update_equiv_gbps": alg * tsteps / s / 1e9}
     if traffic:
+        out["traffic_basis"] = ("L2 egress: FETCH_SIZE + WRITE_SIZE per launch, calibrated; an upper bound on "
+                                "HBM bytes (the memory-side cache may serve part of the reads)")
         out["measured_gbps"] = traffic / s / 1e9
         out["measured_frac"] = traffic / s / 1e9 / PEAK_HBM_GBPS
         out["traffic_over_algorithmic"] = traffic / alg
